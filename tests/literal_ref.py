@@ -1,0 +1,156 @@
+"""Literal reference for one RSA run on an L x L torus (arXiv:1810.06800).
+
+Test tool, independent of both the C oracle and the GPU library.  Everything
+is recomputed from scratch after every deposit, straight from the definition:
+
+* the available placements are found by testing all 2*L*L (o, y, x) for k
+  empty sites (Sec. II.B "viable" placements), listed in canonical order
+  P = o*L*L + y*L + x;
+* the placement of rank floor(u * A / 2^64) is taken, u from Philox4x32-10
+  keyed by the seed with counter (t, sample, 0, 0);
+* wrapping is found by a breadth-first search of every cluster of occupied
+  sites that assigns unwrapped coordinates; an edge whose two ends disagree
+  with their unwrapped offset closes a cycle that winds round the torus
+  (Sec. II.D, Newman-Ziff style).
+
+Only for tiny lattices (L <= 12 or so).
+"""
+from __future__ import annotations
+
+from collections import deque
+
+import numpy as np
+
+MASK32 = 0xFFFFFFFF
+MASK64 = 0xFFFFFFFFFFFFFFFF
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al., SC'11) on Python integers."""
+    x0, x1, x2, x3 = ctr
+    k0, k1 = key
+    for rnd in range(10):
+        if rnd:
+            k0 = (k0 + 0x9E3779B9) & MASK32
+            k1 = (k1 + 0xBB67AE85) & MASK32
+        p0 = 0xD2511F53 * x0
+        p1 = 0xCD9E8D57 * x2
+        x0, x1, x2, x3 = ((p1 >> 32) ^ x1 ^ k0, p1 & MASK32, (p0 >> 32) ^ x3 ^ k1, p0 & MASK32)
+    return x0, x1, x2, x3
+
+
+def mix64(z: int) -> int:
+    """SplitMix64 finalizer (Steele, Lea, Flood 2014)."""
+    z &= MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def draw_u(seed: int, sample: int, t: int) -> int:
+    r = philox4x32_10((t & MASK32, sample & MASK32, 0, 0), (seed & MASK32, (seed >> 32) & MASK32))
+    return r[0] | (r[1] << 32)
+
+
+def available(occ: np.ndarray, k: int, h_only: bool = False) -> list[int]:
+    """Canonical indices of every placement whose k sites are all empty."""
+    L = occ.shape[0]
+    free = ~occ
+    fits_h = np.ones((L, L), dtype=bool)
+    fits_v = np.ones((L, L), dtype=bool)
+    for i in range(k):
+        fits_h &= np.roll(free, -i, axis=1)  # site (y, x+i)
+        fits_v &= np.roll(free, -i, axis=0)  # site (y+i, x)
+    if h_only:
+        fits_v[:] = False
+    idx = list(np.flatnonzero(fits_h.ravel()))
+    idx += [L * L + int(i) for i in np.flatnonzero(fits_v.ravel())]
+    return [int(i) for i in idx]
+
+
+def clusters_and_windings(occ: np.ndarray):
+    """Label clusters of occupied sites (4-neighbour adjacency on the torus)
+    and report, per cluster, whether some closed path winds in x / in y."""
+    L = occ.shape[0]
+    label = -np.ones((L, L), dtype=np.int64)
+    pos = {}
+    out = []
+    for sy in range(L):
+        for sx in range(L):
+            if not occ[sy, sx] or label[sy, sx] >= 0:
+                continue
+            c = len(out)
+            wx = wy = False
+            label[sy, sx] = c
+            pos[(sy, sx)] = (sx, sy)
+            q = deque([(sy, sx)])
+            size = 0
+            while q:
+                y, x = q.popleft()
+                size += 1
+                ux, uy = pos[(y, x)]
+                for ex, ey in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                    ny, nx = (y + ey) % L, (x + ex) % L
+                    if not occ[ny, nx]:
+                        continue
+                    want = (ux + ex, uy + ey)
+                    if label[ny, nx] < 0:
+                        label[ny, nx] = c
+                        pos[(ny, nx)] = want
+                        q.append((ny, nx))
+                    else:
+                        have = pos[(ny, nx)]
+                        if have[0] != want[0]:
+                            wx = True
+                        if have[1] != want[1]:
+                            wy = True
+            out.append((size, wx, wy))
+    return label, out
+
+
+def run(L: int, k: int, seed: int, sample: int, h_only: bool = False) -> dict:
+    occ = np.zeros((L, L), dtype=bool)
+    owner = -np.ones((L, L), dtype=np.int64)
+    seq = []
+    n_x = n_y = -1
+    seq_hash = 0
+    t = 0
+    while True:
+        av = available(occ, k, h_only)
+        A = len(av)
+        if A == 0:
+            break
+        u = draw_u(seed, sample, t)
+        rank = (u * A) >> 64
+        P = av[rank]
+        seq.append(P)
+        seq_hash = (seq_hash + mix64((t << 32) | P)) & MASK64
+        o, rem = divmod(P, L * L)
+        y, x = divmod(rem, L)
+        for i in range(k):
+            sy, sx = ((y + i) % L, x) if o else (y, (x + i) % L)
+            assert not occ[sy, sx]
+            occ[sy, sx] = True
+            owner[sy, sx] = t
+        _, cl = clusters_and_windings(occ)
+        if n_x < 0 and any(c[1] for c in cl):
+            n_x = t + 1
+        if n_y < 0 and any(c[2] for c in cl):
+            n_y = t + 1
+        t += 1
+    _, cl = clusters_and_windings(occ)
+    defined = [v for v in (n_x, n_y) if v > 0]
+    occ_hash = 0
+    for s in np.flatnonzero(owner.ravel() >= 0):
+        occ_hash = (occ_hash + mix64((int(s) << 32) | int(owner.ravel()[s]))) & MASK64
+    return {
+        "n_jam": t,
+        "n_wrap_x": n_x,
+        "n_wrap_y": n_y,
+        "n_wrap_any": min(defined) if defined else -1,
+        "occ_hash": occ_hash,
+        "seq_hash": seq_hash,
+        "seq": seq,
+        "n_clusters_jam": len(cl),
+        "n_nonwrapping_jam": sum(1 for c in cl if not (c[1] or c[2])),
+    }
