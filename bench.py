@@ -1,0 +1,182 @@
+"""Benchmark: deposits/s of RSA of linear k-mers to jamming with first-wrap
+(p_c) tracking on one MI355X, through the C ABI.
+
+One step = one batch of the whole hot path (init, draw, select, deposit and
+clear, contacts + union-find + wrap check, result) over the workload, from
+descriptors in host memory to results back; every input lives in HBM while
+the kernels run.  The default workload is L = 1024, k = 64, 1024 samples
+(seeds 0..1023): the plain-path-at-scale configuration.
+
+The JSON line also carries
+  roofline      the persistent kernel's algorithmic bytes per launch (the
+                model in include/rsa.h, summed over the batch) divided by its
+                HIP-event duration, against 8 TB/s HBM
+  cpu_baseline  the serial CPU oracle on a bounded sample of the same
+                workload on the host's cores (rank 0, N = 1 only)
+  plain         the per-sample-launch form on a subset of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1810_06800_amd/csrc/rsa_kernels.hip", "paper_1810_06800_amd/csrc/rsa_device.h"]
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_digest") != kernel_digest():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def describe(workload: str, descs) -> str:
+    shapes = sorted({(d[0], d[1]) for d in descs})
+    if len(shapes) == 1:
+        L, k = shapes[0]
+        return f"RSA k-mers to jamming, L={L} k={k}, {len(descs)} samples"
+    return f"RSA k-mers to jamming, {len(descs)} samples over (L,k) in {shapes}"
+
+
+def cpu_baseline(descs, gpu_results, budget_s: float):
+    """Time the oracle on a bounded sample of the workload; check parity on it."""
+    import oracle
+
+    threads = os.cpu_count() or 1
+    # size the sample from a short single-sample probe: about budget_s of CPU work
+    t0 = time.perf_counter()
+    oracle.run_many(descs[:1], threads=1)
+    one = max(time.perf_counter() - t0, 1e-4)
+    n = max(threads, min(len(descs), int(budget_s / one)))
+    n = min(n, len(descs))
+    sample = descs[:n]
+    t0 = time.perf_counter()
+    res = oracle.run_many(sample, threads=threads)
+    wall = time.perf_counter() - t0
+    deposits = sum(r["n_jam"] for r in res)
+    fields = ("n_jam", "n_wrap_x", "n_wrap_y", "n_wrap_any", "occ_hash", "seq_hash", "alg_bytes")
+    exact = sum(all(g[f] == w[f] for f in fields) for g, w in zip(gpu_results[:n], res))
+    return {"value": deposits / wall, "unit": "deposits/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {len(descs)} samples, serial per sample, one per thread",
+            "wall_s": round(wall, 3), "parity": f"{exact}/{n} bit-exact"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="plain_scale")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-sample launch form")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="CPU seconds of oracle work")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): samples are independent, "
+              "so several GPUs would each run their own share; no multi-GPU path is built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1810_06800_amd import rsa, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    descs = workloads.CONFIGS[args.workload]()
+    ctx = rsa.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        b = ctx.run_batch(descs)
+        ms = ctx.elapsed_ms(b)
+        return ctx.results(b), ms
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    results = None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        results, ms = step()
+        kernel_ms.append(ms)
+        print(f"# step {i}: kernel {ms:.2f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bad = [r for r in results if r["status"] != 0]
+    if bad:
+        raise RuntimeError(f"{len(bad)} samples failed, first status {bad[0]['status']}")
+    deposits = sum(r["n_jam"] for r in results)
+    alg_bytes = sum(r["alg_bytes"] for r in results)
+    value = deposits * args.steps / wall
+    avg_ms = sum(kernel_ms) / len(kernel_ms)
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload)
+    out = {
+        "metric": "deposits/s to jamming with p_c tracking",
+        "value": value,
+        "unit": "deposits/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": describe(args.workload, descs), "name": args.workload,
+                   "samples": len(descs), "deposits_per_step": deposits,
+                   "kernel_ms_per_step": avg_ms, "kernel_deposits_per_s": deposits / (avg_ms * 1e-3)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "rsa_persistent", "alg_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_plain:
+        sub = descs[: min(len(descs), 64)]
+        ctx.set_option(rsa.OPT_MODE, rsa.MODE_PLAIN)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pres = ctx.run(sub)
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t1
+        ctx.set_option(rsa.OPT_MODE, rsa.MODE_BATCHED)
+        same = sum(p == r for p, r in zip(pres, results[: len(sub)]))
+        out["plain"] = {"value": sum(r["n_jam"] for r in pres) / pw, "unit": "deposits/s",
+                        "samples": len(sub), "launches": len(sub), "streams": 4,
+                        "identical_to_batched": f"{same}/{len(sub)}"}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(descs, results, args.cpu_budget)
+    else:
+        out["cpu_baseline"] = None
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * rsa.h -- C ABI of the MI355X (gfx950) library for random sequential
+ * adsorption (RSA) of linear k-mers on an L x L torus, run to jamming with
+ * first-wrap (percolation) tracking.
+ *
+ * Paper: Slutskii, Barash, Tarasevich, "Percolation and jamming of random
+ * sequential adsorption samples of large linear k-mers on a square lattice",
+ * arXiv:1810.06800.
+ *
+ * Problem statement (Sec. II.A): k-mers -- straight needles covering k
+ * consecutive sites of one row (horizontal, H) or one column (vertical, V) --
+ * are deposited on an L x L square lattice with periodic boundaries (a
+ * torus) by isotropic RSA until jamming, i.e. until no k-mer fits.  Sec. II.B
+ * draws each new k-mer among the placements where it still fits; Sec. II.C
+ * labels clusters by union-find; Sec. II.D detects the first cluster that
+ * wraps round the torus.  Each sample is one independent run (Sec. II.A).
+ * The caller derives the concentrations p_c = n_wrap_any*k/L^2 (first wrap,
+ * in one or both directions, Sec. II.D) and p_j = n_jam*k/L^2 (jamming).
+ *
+ * Canonical sampling (the paper's RNG cannot be reproduced, so it is fixed
+ * here and every result is a deterministic function of the descriptor):
+ *   placement p = (o, y, x), o = 0 (H: sites (y, x+i)) or 1 (V: (y+i, x)),
+ *   i = 0..k-1 mod L; canonical index P = o*L*L + y*L + x;
+ *   step t: (r0..r3) = Philox4x32-10(key = (seed mod 2^32, seed >> 32),
+ *   counter = (t, sample, 0, 0)); u = r0 + 2^32*r1;
+ *   rank = floor(u * A_t / 2^64) among the A_t available placements in
+ *   canonical order.
+ *
+ * Threading: a context may be used from one host thread at a time.  All
+ * functions return negative rsa_status codes on failure; no C++ exception
+ * crosses this boundary.
+ */
+#ifndef RSA_H
+#define RSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSA_ABI_VERSION 1
+
+/* Status codes (0 or negative). */
+enum rsa_status {
+    RSA_OK = 0,
+    RSA_EINVAL = -1,    /* bad argument; nothing was enqueued               */
+    RSA_ENOMEM = -2,    /* device memory budget or allocation exhausted     */
+    RSA_EDEVICE = -3,   /* a HIP call failed; the context is poisoned       */
+    RSA_ENOTREADY = -4, /* rsa_results(wait = 0) before the batch finished  */
+    RSA_EBUSY = -5,     /* resource in use                                  */
+    RSA_ENOTFOUND = -6  /* unknown or already collected batch id            */
+};
+
+/* Per-sample flags. */
+enum rsa_flags {
+    /* Vertical placements start unavailable: L independent rings of length L
+     * (one-dimensional RSA).  Test mode. */
+    RSA_FLAG_H_ONLY = 1u << 0,
+    /* Also report the number of clusters and of non-wrapping clusters at
+     * jamming (Appendix A: the latter is always 0).  Keeps cluster labelling
+     * running to jamming instead of stopping once both wrap steps are known. */
+    RSA_FLAG_TRACK_CLUSTERS = 1u << 1
+};
+
+/* Opaque context.  Owns every device allocation made on its behalf. */
+typedef struct rsa_ctx rsa_ctx;
+
+/* One independent run (Sec. II.A).  1 <= k <= L <= 32768; flags from
+ * rsa_flags.  (seed, sample) select the Philox stream described above. */
+typedef struct {
+    uint32_t L, k;
+    uint64_t seed;
+    uint32_t sample, flags;
+} rsa_sample_t;
+
+/* Result of one run (80 bytes).  Counts are 1-based deposit numbers; -1 means
+ * "never" (possible for one direction on small tori).
+ *   n_jam        k-mers on the lattice at jamming
+ *   n_wrap_x/_y  deposit after which some cluster first wraps in x / in y
+ *                (a closed path whose unwrapped displacement has a non-zero
+ *                x / y component)
+ *   n_wrap_any   the smaller of the defined wrap counts (the paper's p_c)
+ *   occ_hash     sum over occupied sites s of mix64((s << 32) | id(s)) mod
+ *                2^64, id(s) = deposit number of the k-mer covering s and
+ *                mix64 the SplitMix64 finalizer (Steele, Lea, Flood 2014)
+ *   seq_hash     sum over steps t of mix64((t << 32) | P_t) mod 2^64
+ *   n_clusters_jam, n_nonwrapping_jam   cluster census at jamming, -1 unless
+ *                RSA_FLAG_TRACK_CLUSTERS
+ *   status       0, or a negative rsa_status for this sample
+ *   tile         schedule the batch planner chose for this sample
+ *   alg_bytes    algorithmic-byte model of the run: 4 B/site map
+ *                initialisation and both availability bitmaps; per deposit
+ *                4k (map) + 4(2k+2) (contacts) + 8*ceil(L/64) (select row)
+ *                + 16 (k-mer record); 16 B per availability word changed
+ *   wchg_words   availability words whose value changed, summed over steps
+ */
+typedef struct {
+    int64_t n_jam, n_wrap_x, n_wrap_y, n_wrap_any;
+    uint64_t occ_hash, seq_hash;
+    int32_t n_clusters_jam, n_nonwrapping_jam;
+    int32_t status, tile;
+    uint64_t alg_bytes, wchg_words;
+} rsa_result_t;
+
+/* Optional device allocator.  alloc returns device memory of at least
+ * `bytes` (256-byte aligned) or NULL; free releases it.  Both are called on
+ * the thread that calls into the library, never from a device callback. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, size_t bytes, void *user);
+    void *user;
+} rsa_allocator_t;
+
+/* Create a context on HIP device `device`.
+ *   hbm_budget_bytes  upper bound on device memory the context may hold at
+ *                     once (0 = 90 % of the device's memory)
+ *   alloc             NULL = hipMalloc/hipFree; otherwise used for every
+ *                     device allocation (the pointer is copied)
+ * Writes the new context to *out.  RSA_EINVAL for a NULL out or a bad device,
+ * RSA_EDEVICE if HIP fails. */
+int rsa_create(rsa_ctx **out, int device, uint64_t hbm_budget_bytes,
+               const rsa_allocator_t *alloc);
+
+/* Device bytes one resident sample of shape (L, k) needs: two availability
+ * bitmaps of L*ceil(L/64) words, the int32 site map, k-mer records for up to
+ * L*L/k + 1 deposits, and 256-byte alignment.  0 for an invalid shape. */
+size_t rsa_footprint_bytes(uint32_t L, uint32_t k);
+
+/* Enqueue n independent samples on `hip_stream` (a hipStream_t; NULL = the
+ * null stream) and return at once.  The descriptors are copied before the
+ * call returns; the caller keeps ownership of `s`.  Results of one batch do
+ * not depend on its composition, its order or the schedule chosen.
+ * *batch_id receives a handle for rsa_results.
+ * n == 0 is an empty batch.  RSA_EINVAL (nothing enqueued) for s == NULL with
+ * n > 0, any invalid descriptor, a flag outside rsa_flags, or a lattice whose
+ * row counts do not fit the workgroup's LDS; RSA_ENOMEM if the batch does not
+ * fit the budget; RSA_EDEVICE on a HIP failure. */
+int rsa_run_batch(rsa_ctx *ctx, const rsa_sample_t *s, uint32_t n, void *hip_stream,
+                  uint64_t *batch_id);
+
+/* Copy the n results of batch `batch_id` into out[0..n-1] (same order as the
+ * descriptors) and release the batch's device memory.  wait = 1 blocks until
+ * the batch is done; wait = 0 returns RSA_ENOTREADY if it is still running
+ * (the batch stays valid).  RSA_ENOTFOUND for an unknown id, RSA_EINVAL if n
+ * differs from the batch size. */
+int rsa_results(rsa_ctx *ctx, uint64_t batch_id, rsa_result_t *out, uint32_t n, int wait);
+
+/* Device time of batch `batch_id`'s kernels in milliseconds, from HIP events
+ * recorded on its stream right before the first and after the last kernel
+ * (descriptor and result copies excluded).  Blocks until the kernels are
+ * done; valid until rsa_results collects the batch.  RSA_ENOTFOUND for an
+ * unknown id. */
+int rsa_batch_elapsed_ms(rsa_ctx *ctx, uint64_t batch_id, float *ms);
+
+/* Wait for all work of the context, free every allocation and the context.
+ * NULL is ignored. */
+void rsa_destroy(rsa_ctx *ctx);
+
+/* Static description of a status code. */
+const char *rsa_strerror(int code);
+
+/* Message of the context's most recent failure ("" if none).  The string
+ * stays valid until the next call on the context. */
+const char *rsa_last_error(rsa_ctx *ctx);
+
+/* Context options (rsa_set_option / rsa_get_option):
+ *   RSA_OPT_MODE   RSA_MODE_BATCHED (default): one persistent launch per
+ *                  batch pulls samples from a device work queue, longest
+ *                  first; RSA_MODE_PLAIN: one launch per sample with a fixed
+ *                  schedule, round-robin over four streams forked from and
+ *                  joined back to the caller's stream (the comparison form)
+ *   RSA_OPT_TILE   -1 (default) = schedule from the autotune table, else a
+ *                  fixed schedule id in [0, RSA_NUM_TILES)
+ *   RSA_OPT_GRAPH  1 (default) = batched launches are captured into a
+ *                  hipGraph once per shape signature and replayed; 0 = direct
+ *   RSA_OPT_SLOTS  0 (default) = as many resident workgroups as fit, else
+ *                  an upper bound on them
+ * Unknown options or values: RSA_EINVAL. */
+enum rsa_option { RSA_OPT_MODE = 1, RSA_OPT_TILE = 2, RSA_OPT_GRAPH = 3, RSA_OPT_SLOTS = 4 };
+enum rsa_mode { RSA_MODE_BATCHED = 0, RSA_MODE_PLAIN = 1 };
+int rsa_set_option(rsa_ctx *ctx, int option, int64_t value);
+int rsa_get_option(rsa_ctx *ctx, int option, int64_t *value);
+
+/* Number of schedules ("tiles") the library implements, and the one the
+ * autotune table picks for a shape. */
+int rsa_num_tiles(void);
+int rsa_tile_for_shape(uint32_t L, uint32_t k);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

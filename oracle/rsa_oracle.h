@@ -44,6 +44,9 @@ extern "C" {
 /* Flag: vertical placements start unavailable, so the lattice is L
  * independent rings of length L (one-dimensional RSA).  Test mode. */
 #define RSAO_FLAG_H_ONLY 1u
+/* Flag accepted for interface symmetry with the GPU library: the oracle
+ * always takes the cluster census at jamming. */
+#define RSAO_FLAG_TRACK_CLUSTERS 2u
 
 /* One independent run (Sec. II.A).  1 <= k <= L <= 32768. */
 typedef struct {

@@ -1,0 +1,629 @@
+// rsa_capi.hip -- host runtime behind the C ABI of include/rsa.h.
+//
+// A batch is planned into groups of samples that share a schedule ("tile"),
+// each group becomes one persistent launch over its own device work queue,
+// and all groups of a batch run as parallel nodes of one hipGraph (instantiated
+// once per launch signature and replayed).  Device memory comes from a
+// per-context pool of slabs, through the caller's allocator when one is given.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rsa.h"
+#include "rsa_device.h"
+
+namespace rsa {
+extern const void *kPersistentKernels[kNumTiles];
+extern const void *kResetKernel;
+}  // namespace rsa
+
+using namespace rsa;
+
+static_assert(sizeof(rsa_result_t) == sizeof(DevResult), "result layout");
+static_assert(sizeof(rsa_result_t) == 80, "result size");
+static_assert(sizeof(rsa_sample_t) == 24, "sample size");
+
+namespace {
+
+constexpr int kPlainStreams = 4;
+
+struct Group {
+    int tile;
+    uint32_t first, count;   // range in the planned descriptor array
+    uint32_t grid;
+    uint32_t lds;
+    size_t stride;           // slab bytes per resident workgroup
+    size_t slab_off;         // offset of this group's slabs in the batch allocation
+};
+
+struct Block {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Batch {
+    uint64_t id = 0;
+    uint32_t n = 0;
+    Block mem;
+    DevDesc *h_desc = nullptr;      // pinned
+    rsa_result_t *h_res = nullptr;  // pinned
+    hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_done = nullptr;
+    std::vector<Group> groups;
+    int mode = RSA_MODE_BATCHED;
+};
+
+struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct rsa_ctx {
+    int device = 0;
+    int cus = 0;
+    size_t lds_max = 0;
+    uint64_t budget = 0;
+    uint64_t held = 0;   // bytes currently allocated (in use + pooled)
+    bool custom = false;
+    rsa_allocator_t alloc{};
+    bool poisoned = false;
+    std::string last_error;
+    uint64_t next_id = 1;
+    std::map<uint64_t, Batch *> batches;
+    std::vector<Block> pool;   // free device blocks
+    std::vector<GraphEntry> graphs;
+    int64_t opt_mode = RSA_MODE_BATCHED, opt_tile = -1, opt_graph = 1, opt_slots = 0;
+    hipStream_t plain[kPlainStreams] = {};
+    hipEvent_t fork = nullptr, join[kPlainStreams] = {};
+    int resident[kNumTiles][4] = {};   // cached occupancy per tile and LDS class
+};
+
+namespace {
+
+int fail(rsa_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->last_error = msg;
+    return code;
+}
+
+int hip_fail(rsa_ctx *c, hipError_t e, const char *what)
+{
+    if (c) {
+        c->poisoned = true;
+        c->last_error = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return RSA_EDEVICE;
+}
+
+#define HIP_TRY(ctx, expr)                                  \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+bool valid_sample(const rsa_sample_t &s)
+{
+    const uint32_t known = RSA_FLAG_H_ONLY | RSA_FLAG_TRACK_CLUSTERS;
+    return s.k >= 1 && s.k <= s.L && s.L <= 32768 && (s.flags & ~known) == 0;
+}
+
+// Schedule heuristic: waves that share the select/clear of one sample grow
+// with the k x k block a deposit clears.
+int default_tile(uint32_t L, uint32_t k)
+{
+    (void)L;
+    if (k <= 64) return 0;
+    if (k <= 128) return 1;
+    if (k <= 256) return 2;
+    if (k <= 1024) return 3;
+    return 4;
+}
+
+// Relative cost of a sample: deposits (about 0.7 L^2 / k) times the words a
+// deposit clears spread over the tile's waves, plus a per-step latency floor.
+double sample_cost(uint32_t L, uint32_t k, int tile)
+{
+    double steps = 0.7 * (double)L * L / k;
+    double words = (double)k * ((double)k / 64.0 + 1.0);
+    return steps * (8.0 + words / (64.0 * kTileWaves[tile]));
+}
+
+void *dev_alloc(rsa_ctx *c, size_t bytes)
+{
+    if (c->custom) return c->alloc.alloc(bytes, c->alloc.user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_free(rsa_ctx *c, void *p, size_t bytes)
+{
+    if (!p) return;
+    if (c->custom)
+        c->alloc.free(p, bytes, c->alloc.user);
+    else
+        (void)hipFree(p);
+}
+
+// Best-fit block from the pool, else a fresh allocation within the budget.
+bool take_block(rsa_ctx *c, size_t bytes, Block &out)
+{
+    int best = -1;
+    for (size_t i = 0; i < c->pool.size(); ++i) {
+        size_t b = c->pool[i].bytes;
+        if (b >= bytes && b <= bytes + bytes / 4 && (best < 0 || b < c->pool[best].bytes)) best = (int)i;
+    }
+    if (best >= 0) {
+        out = c->pool[best];
+        c->pool.erase(c->pool.begin() + best);
+        return true;
+    }
+    // release pooled blocks until the new one fits the budget
+    while (c->held + bytes > c->budget && !c->pool.empty()) {
+        Block b = c->pool.back();
+        c->pool.pop_back();
+        dev_free(c, b.ptr, b.bytes);
+        c->held -= b.bytes;
+    }
+    if (c->held + bytes > c->budget) return false;
+    void *p = dev_alloc(c, bytes);
+    if (!p) {
+        // the caller's allocator or the device is out of memory: free the pool and retry
+        while (!c->pool.empty()) {
+            Block b = c->pool.back();
+            c->pool.pop_back();
+            dev_free(c, b.ptr, b.bytes);
+            c->held -= b.bytes;
+        }
+        p = dev_alloc(c, bytes);
+        if (!p) return false;
+    }
+    c->held += bytes;
+    out.ptr = p;
+    out.bytes = bytes;
+    return true;
+}
+
+void give_block(rsa_ctx *c, Block b)
+{
+    if (b.ptr) c->pool.push_back(b);
+}
+
+int resident_blocks(rsa_ctx *c, int tile, uint32_t lds)
+{
+    int nb = 0;
+    int threads = 64 * (kTileWaves[tile] + 1);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kPersistentKernels[tile], threads, lds) !=
+            hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb * c->cus;
+}
+
+DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out)
+{
+    DevDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.L = s.L;
+    d.k = s.k;
+    d.seed = s.seed;
+    d.sample = s.sample;
+    d.flags = s.flags;
+    d.out = out;
+    d.wd = (s.L + 63) / 64;
+    d.fL = make_fastdiv(s.L);
+    d.fk = make_fastdiv(s.k);
+    d.fC = make_fastdiv(2 * s.k + 2);
+    return d;
+}
+
+void destroy_batch(rsa_ctx *c, Batch *b)
+{
+    if (!b) return;
+    if (b->ev_start) (void)hipEventDestroy(b->ev_start);
+    if (b->ev_end) (void)hipEventDestroy(b->ev_end);
+    if (b->ev_done) (void)hipEventDestroy(b->ev_done);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    if (b->h_res) (void)hipHostFree(b->h_res);
+    give_block(c, b->mem);
+    delete b;
+}
+
+hipGraphExec_t cached_graph(rsa_ctx *c, const std::string &key)
+{
+    for (auto &g : c->graphs)
+        if (g.key == key) return g.exec;
+    return nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *rsa_strerror(int code)
+{
+    switch (code) {
+    case RSA_OK: return "ok";
+    case RSA_EINVAL: return "invalid argument";
+    case RSA_ENOMEM: return "device memory budget exhausted";
+    case RSA_EDEVICE: return "HIP device error";
+    case RSA_ENOTREADY: return "batch not finished";
+    case RSA_EBUSY: return "resource busy";
+    case RSA_ENOTFOUND: return "unknown batch id";
+    default: return "unknown status";
+    }
+}
+
+const char *rsa_last_error(rsa_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+size_t rsa_footprint_bytes(uint32_t L, uint32_t k)
+{
+    if (k < 1 || k > L || L > 32768) return 0;
+    return slab_layout(L, k).total;
+}
+
+int rsa_num_tiles(void) { return kNumTiles; }
+
+int rsa_tile_for_shape(uint32_t L, uint32_t k)
+{
+    if (k < 1 || k > L || L > 32768) return RSA_EINVAL;
+    return default_tile(L, k);
+}
+
+int rsa_create(rsa_ctx **out, int device, uint64_t hbm_budget_bytes, const rsa_allocator_t *alloc)
+{
+    if (!out) return RSA_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RSA_EINVAL;
+    if (alloc && (!alloc->alloc || !alloc->free)) return RSA_EINVAL;
+    rsa_ctx *c = new (std::nothrow) rsa_ctx();
+    if (!c) return RSA_ENOMEM;
+    c->device = device;
+    if (alloc) {
+        c->custom = true;
+        c->alloc = *alloc;
+    }
+    hipDeviceProp_t p;
+    if (hipSetDevice(device) != hipSuccess || hipGetDeviceProperties(&p, device) != hipSuccess) {
+        delete c;
+        return RSA_EDEVICE;
+    }
+    c->cus = p.multiProcessorCount;
+    c->lds_max = p.sharedMemPerBlock;
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)p.totalGlobalMem);
+    for (int t = 0; t < kNumTiles; ++t) {
+        if (hipFuncSetAttribute(kPersistentKernels[t], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(c->lds_max - 64)) != hipSuccess) {
+            delete c;
+            return RSA_EDEVICE;
+        }
+    }
+    for (int i = 0; i < kPlainStreams; ++i) {
+        if (hipStreamCreateWithFlags(&c->plain[i], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming) != hipSuccess) {
+            delete c;
+            return RSA_EDEVICE;
+        }
+    }
+    if (hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return RSA_EDEVICE;
+    }
+    *out = c;
+    return RSA_OK;
+}
+
+int rsa_set_option(rsa_ctx *c, int option, int64_t value)
+{
+    if (!c) return RSA_EINVAL;
+    switch (option) {
+    case RSA_OPT_MODE:
+        if (value != RSA_MODE_BATCHED && value != RSA_MODE_PLAIN) return fail(c, RSA_EINVAL, "bad mode");
+        c->opt_mode = value;
+        return RSA_OK;
+    case RSA_OPT_TILE:
+        if (value < -1 || value >= kNumTiles) return fail(c, RSA_EINVAL, "bad tile");
+        c->opt_tile = value;
+        return RSA_OK;
+    case RSA_OPT_GRAPH:
+        if (value != 0 && value != 1) return fail(c, RSA_EINVAL, "bad graph flag");
+        c->opt_graph = value;
+        return RSA_OK;
+    case RSA_OPT_SLOTS:
+        if (value < 0) return fail(c, RSA_EINVAL, "bad slot bound");
+        c->opt_slots = value;
+        return RSA_OK;
+    default: return fail(c, RSA_EINVAL, "unknown option");
+    }
+}
+
+int rsa_get_option(rsa_ctx *c, int option, int64_t *value)
+{
+    if (!c || !value) return RSA_EINVAL;
+    switch (option) {
+    case RSA_OPT_MODE: *value = c->opt_mode; return RSA_OK;
+    case RSA_OPT_TILE: *value = c->opt_tile; return RSA_OK;
+    case RSA_OPT_GRAPH: *value = c->opt_graph; return RSA_OK;
+    case RSA_OPT_SLOTS: *value = c->opt_slots; return RSA_OK;
+    default: return fail(c, RSA_EINVAL, "unknown option");
+    }
+}
+
+int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_stream, uint64_t *batch_id)
+{
+    if (!c || !batch_id || (n > 0 && !s)) return fail(c, RSA_EINVAL, "null argument");
+    if (c->poisoned) return fail(c, RSA_EDEVICE, "context poisoned by an earlier device error");
+    for (uint32_t i = 0; i < n; ++i)
+        if (!valid_sample(s[i]))
+            return fail(c, RSA_EINVAL, "invalid descriptor at index " + std::to_string(i));
+    hipStream_t stream = (hipStream_t)hip_stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+
+    std::unique_ptr<Batch> b(new Batch());
+    b->n = n;
+    b->mode = (int)c->opt_mode;
+
+    // ---- plan: group by tile, longest samples first inside a group
+    std::vector<int> tiles(n);
+    for (uint32_t i = 0; i < n; ++i)
+        tiles[i] = c->opt_tile >= 0 ? (int)c->opt_tile : default_tile(s[i].L, s[i].k);
+    std::vector<uint32_t> order(n);
+    for (uint32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t bb) {
+        if (tiles[a] != tiles[bb]) return tiles[a] > tiles[bb];
+        return sample_cost(s[a].L, s[a].k, tiles[a]) > sample_cost(s[bb].L, s[bb].k, tiles[bb]);
+    });
+    size_t total = 0;
+    const size_t desc_bytes = align256((size_t)std::max<uint32_t>(n, 1) * sizeof(DevDesc));
+    const size_t res_bytes = align256((size_t)std::max<uint32_t>(n, 1) * sizeof(DevResult));
+    const size_t queue_count = b->mode == RSA_MODE_PLAIN ? std::max<uint32_t>(n, 1) : kNumTiles;
+    const size_t queue_bytes = align256(queue_count * 4);
+    total = desc_bytes + res_bytes + queue_bytes;
+    for (uint32_t i = 0; i < n;) {
+        Group g;
+        g.tile = tiles[order[i]];
+        g.first = i;
+        uint32_t j = i;
+        size_t stride = 0;
+        uint32_t lds = 0;
+        while (j < n && tiles[order[j]] == g.tile) {
+            stride = std::max(stride, slab_layout(s[order[j]].L, s[order[j]].k).total);
+            lds = std::max(lds, lds_layout(s[order[j]].L).total);
+            ++j;
+        }
+        g.count = j - i;
+        g.stride = stride;
+        g.lds = lds;
+        if (lds + 64 > c->lds_max) return fail(c, RSA_EINVAL, "lattice too large for LDS");
+        uint32_t grid;
+        if (b->mode == RSA_MODE_PLAIN) {
+            grid = kPlainStreams;   // one slab per stream: samples on a stream run in order
+        } else {
+            grid = std::min<uint32_t>(g.count, (uint32_t)resident_blocks(c, g.tile, lds));
+            if (c->opt_slots > 0) grid = std::min<uint32_t>(grid, (uint32_t)c->opt_slots);
+        }
+        g.grid = grid;
+        b->groups.push_back(g);
+        i = j;
+    }
+    // fit the slabs into the budget, shrinking the widest groups first
+    auto slab_total = [&]() {
+        size_t t = 0;
+        for (auto &g : b->groups) t += g.stride * g.grid;
+        return t;
+    };
+    while (total + slab_total() > c->budget) {
+        Group *big = nullptr;
+        if (b->mode != RSA_MODE_PLAIN)
+            for (auto &g : b->groups)
+                if (g.grid > 1 && (!big || g.stride * g.grid > big->stride * big->grid)) big = &g;
+        if (!big) return fail(c, RSA_ENOMEM, "batch does not fit the device memory budget");
+        big->grid = std::max<uint32_t>(1, big->grid / 2);
+    }
+    for (auto &g : b->groups) {
+        g.slab_off = total;
+        total += g.stride * g.grid;
+    }
+    if (!take_block(c, total, b->mem)) return fail(c, RSA_ENOMEM, "device allocation failed");
+    uint8_t *base = (uint8_t *)b->mem.ptr;
+    DevDesc *d_desc = (DevDesc *)base;
+    DevResult *d_res = (DevResult *)(base + desc_bytes);
+    uint32_t *d_queue = (uint32_t *)(base + desc_bytes + res_bytes);
+
+    // ---- descriptors (pinned staging), copied before the call returns
+    if (hipHostMalloc((void **)&b->h_desc, desc_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_res, res_bytes, hipHostMallocDefault) != hipSuccess) {
+        destroy_batch(c, b.release());
+        return fail(c, RSA_ENOMEM, "pinned host allocation failed");
+    }
+    for (uint32_t i = 0; i < n; ++i) b->h_desc[i] = make_dev_desc(s[order[i]], order[i]);
+    HIP_TRY(c, hipEventCreate(&b->ev_start));
+    HIP_TRY(c, hipEventCreate(&b->ev_end));
+    HIP_TRY(c, hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
+    if (n > 0)
+        HIP_TRY(c, hipMemcpyAsync(d_desc, b->h_desc, (size_t)n * sizeof(DevDesc),
+                                  hipMemcpyHostToDevice, stream));
+
+    // ---- launches
+    HIP_TRY(c, hipEventRecord(b->ev_start, stream));
+    std::vector<KernelArgs> args;
+    for (auto &g : b->groups) {
+        KernelArgs a;
+        a.descs = d_desc + g.first;
+        a.n = g.count;
+        a.tile = (uint32_t)g.tile;
+        a.queue = d_queue + g.tile;
+        a.slabs = base + g.slab_off;
+        a.slab_stride = g.stride;
+        a.results = d_res;
+        args.push_back(a);
+    }
+    if (n == 0) {
+        // nothing to run
+    } else if (b->mode == RSA_MODE_PLAIN) {
+        // one launch per sample, round-robin over four streams forked from
+        // the caller's stream; one slab per stream
+        uint32_t nq = (uint32_t)queue_count;
+        void *rargs[] = {&d_queue, &nq};
+        HIP_TRY(c, hipLaunchKernel(kResetKernel, dim3((nq + 255) / 256), dim3(256), rargs, 0, stream));
+        HIP_TRY(c, hipEventRecord(c->fork, stream));
+        for (int i = 0; i < kPlainStreams; ++i) HIP_TRY(c, hipStreamWaitEvent(c->plain[i], c->fork, 0));
+        uint32_t idx = 0;
+        for (auto &g : b->groups) {
+            int threads = 64 * (kTileWaves[g.tile] + 1);
+            for (uint32_t j = 0; j < g.count; ++j, ++idx) {
+                int si = (int)(idx % kPlainStreams);
+                KernelArgs a;
+                a.descs = d_desc + g.first + j;
+                a.n = 1;
+                a.tile = (uint32_t)g.tile;
+                a.queue = d_queue + g.first + j;
+                a.slabs = base + g.slab_off + (size_t)si * g.stride;
+                a.slab_stride = 0;
+                a.results = d_res;
+                void *kargs[] = {&a};
+                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.tile], dim3(1), dim3(threads), kargs,
+                                           g.lds, c->plain[si]));
+            }
+        }
+        for (int i = 0; i < kPlainStreams; ++i) {
+            HIP_TRY(c, hipEventRecord(c->join[i], c->plain[i]));
+            HIP_TRY(c, hipStreamWaitEvent(stream, c->join[i], 0));
+        }
+    } else {
+        // one graph: reset the queues, then every group's persistent launch
+        std::string key;
+        key.reserve(64 * args.size());
+        for (size_t i = 0; i < args.size(); ++i) {
+            const Group &g = b->groups[i];
+            char buf[64];
+            std::snprintf(buf, sizeof(buf), "%d:%u:%u|", g.tile, g.grid, g.lds);
+            key += buf;
+            key.append((const char *)&args[i], sizeof(KernelArgs));
+        }
+        uint32_t nq = kNumTiles;
+        if (c->opt_graph) {
+            hipGraphExec_t exec = cached_graph(c, key);
+            if (!exec) {
+                hipGraph_t graph;
+                HIP_TRY(c, hipGraphCreate(&graph, 0));
+                hipGraphNode_t reset;
+                hipKernelNodeParams rp;
+                std::memset(&rp, 0, sizeof(rp));
+                void *rargs[] = {&d_queue, &nq};
+                rp.func = (void *)kResetKernel;
+                rp.gridDim = dim3(1);
+                rp.blockDim = dim3(64);
+                rp.kernelParams = rargs;
+                HIP_TRY(c, hipGraphAddKernelNode(&reset, graph, nullptr, 0, &rp));
+                for (size_t i = 0; i < args.size(); ++i) {
+                    const Group &g = b->groups[i];
+                    hipKernelNodeParams kp;
+                    std::memset(&kp, 0, sizeof(kp));
+                    void *kargs[] = {&args[i]};
+                    kp.func = (void *)kPersistentKernels[g.tile];
+                    kp.gridDim = dim3(g.grid);
+                    kp.blockDim = dim3(64 * (kTileWaves[g.tile] + 1));
+                    kp.sharedMemBytes = g.lds;
+                    kp.kernelParams = kargs;
+                    hipGraphNode_t node;
+                    HIP_TRY(c, hipGraphAddKernelNode(&node, graph, &reset, 1, &kp));
+                }
+                hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+                if (c->graphs.size() >= 8) {
+                    (void)hipGraphExecDestroy(c->graphs.front().exec);
+                    c->graphs.erase(c->graphs.begin());
+                }
+                c->graphs.push_back(GraphEntry{key, exec});
+            }
+            HIP_TRY(c, hipGraphLaunch(exec, stream));
+        } else {
+            void *rargs[] = {&d_queue, &nq};
+            HIP_TRY(c, hipLaunchKernel(kResetKernel, dim3(1), dim3(64), rargs, 0, stream));
+            for (size_t i = 0; i < args.size(); ++i) {
+                const Group &g = b->groups[i];
+                void *kargs[] = {&args[i]};
+                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.tile], dim3(g.grid),
+                                           dim3(64 * (kTileWaves[g.tile] + 1)), kargs, g.lds, stream));
+            }
+        }
+    }
+    HIP_TRY(c, hipEventRecord(b->ev_end, stream));
+    if (n > 0)
+        HIP_TRY(c, hipMemcpyAsync(b->h_res, d_res, (size_t)n * sizeof(DevResult), hipMemcpyDeviceToHost,
+                                  stream));
+    HIP_TRY(c, hipEventRecord(b->ev_done, stream));
+    b->id = c->next_id++;
+    *batch_id = b->id;
+    c->batches[b->id] = b.get();
+    b.release();
+    return RSA_OK;
+}
+
+int rsa_results(rsa_ctx *c, uint64_t batch_id, rsa_result_t *out, uint32_t n, int wait)
+{
+    if (!c) return RSA_EINVAL;
+    auto it = c->batches.find(batch_id);
+    if (it == c->batches.end()) return fail(c, RSA_ENOTFOUND, "unknown batch id");
+    Batch *b = it->second;
+    if (n != b->n || (n > 0 && !out)) return fail(c, RSA_EINVAL, "result count differs from batch size");
+    if (wait) {
+        hipError_t e = hipEventSynchronize(b->ev_done);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    } else {
+        hipError_t e = hipEventQuery(b->ev_done);
+        if (e == hipErrorNotReady) return RSA_ENOTREADY;
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventQuery");
+    }
+    if (n > 0) std::memcpy(out, b->h_res, (size_t)n * sizeof(rsa_result_t));
+    c->batches.erase(it);
+    destroy_batch(c, b);
+    return RSA_OK;
+}
+
+int rsa_batch_elapsed_ms(rsa_ctx *c, uint64_t batch_id, float *ms)
+{
+    if (!c || !ms) return RSA_EINVAL;
+    auto it = c->batches.find(batch_id);
+    if (it == c->batches.end()) return fail(c, RSA_ENOTFOUND, "unknown batch id");
+    Batch *b = it->second;
+    hipError_t e = hipEventSynchronize(b->ev_end);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    e = hipEventElapsedTime(ms, b->ev_start, b->ev_end);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+    return RSA_OK;
+}
+
+void rsa_destroy(rsa_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c->batches) destroy_batch(c, kv.second);
+    c->batches.clear();
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto &b : c->pool) dev_free(c, b.ptr, b.bytes);
+    for (int i = 0; i < kPlainStreams; ++i) {
+        if (c->plain[i]) (void)hipStreamDestroy(c->plain[i]);
+        if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+    }
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    delete c;
+}
+
+}  // extern "C"

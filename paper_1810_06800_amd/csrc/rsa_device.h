@@ -1,0 +1,141 @@
+// rsa_device.h -- types shared by the host runtime and the gfx950 kernels of
+// the k-mer RSA library (arXiv:1810.06800).  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rsa {
+
+// Division by a run-time constant d <= 2^31 via a 32-bit multiply-high
+// (Granlund and Montgomery, PLDI'94, round-up method): q = (mulhi(n, m) + n) >> l
+// with l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1; exact for every
+// 32-bit n.
+struct FastDiv {
+    uint32_t d, m, l, pad;
+};
+
+__host__ __device__ inline FastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+    return FastDiv{d, (uint32_t)m, l, 0};
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
+{
+    uint64_t t = __umulhi(n, f.m);
+    return (uint32_t)((t + n) >> f.l);
+}
+
+// One sample as the kernels see it (80 bytes).
+struct DevDesc {
+    uint32_t L, k;
+    uint64_t seed;
+    uint32_t sample, flags;
+    uint32_t out;    // index into the result array
+    uint32_t wd;     // 64-bit words per bitmap row, ceil(L/64)
+    FastDiv fL;      // division by L
+    FastDiv fk;      // division by k
+    FastDiv fC;      // division by 2k+2 (contacts per k-mer)
+};
+
+// Mirrors rsa_result_t of include/rsa.h (80 bytes).
+struct DevResult {
+    int64_t n_jam, n_wrap_x, n_wrap_y, n_wrap_any;
+    uint64_t occ_hash, seq_hash;
+    int32_t n_clusters_jam, n_nonwrapping_jam;
+    int32_t status, tile;
+    uint64_t alg_bytes, wchg_words;
+};
+
+// Per-sample device state, one slab per resident workgroup:
+//   avail[0], avail[1]  availability bitmaps of H / V placements, row-major,
+//                       L rows of wd words, bit x%64 of word x/64 = anchor x
+//   map                 int32 site -> k-mer id (deposit number), -1 = empty
+//   node                per k-mer union-find record {parent, dx, dy, meta}:
+//                       (dx, dy) = anchor minus the parent's anchor, unwrapped;
+//                       meta (roots only) = rank | wraps-in-x << 8 | -in-y << 9
+//   kmer                per k-mer anchor site index | orientation << 31
+struct SlabLayout {
+    size_t avail0, avail1, map, node, kmer, total;
+};
+
+__host__ __device__ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+__host__ __device__ inline SlabLayout slab_layout(uint32_t L, uint32_t k)
+{
+    SlabLayout s;
+    size_t wd = (L + 63) / 64;
+    size_t cap = (size_t)L * L / k + 1;
+    size_t off = 0;
+    s.avail0 = off; off = align256(off + (size_t)L * wd * 8);
+    s.avail1 = off; off = align256(off + (size_t)L * wd * 8);
+    s.map = off;    off = align256(off + (size_t)L * L * 4);
+    s.node = off;   off = align256(off + cap * 16);
+    s.kmer = off;   off = align256(off + cap * 4);
+    s.total = off;
+    return s;
+}
+
+// Fixed capacities of the per-workgroup LDS areas.
+constexpr uint32_t kRing = 512;    // placements in flight between the waves
+constexpr uint32_t kBatch = 64;    // deposits the labelling wave takes at once
+constexpr uint32_t kEdges = 256;   // contact edges per labelling chunk
+constexpr uint32_t kSlots = 640;   // local union-find slots: a batch plus two per edge
+constexpr uint32_t kHash = 1024;   // open-addressing table of global roots
+
+// LDS layout for a sample of side L (bytes from the start of dynamic LDS).
+struct LdsLayout {
+    uint32_t hdr, cnt0, cnt1, cnt2, ring, banc, edges, slots, hash, total;
+    uint32_t n1, n2;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(uint32_t L)
+{
+    LdsLayout s;
+    uint32_t rows = 2 * L;
+    s.n1 = (rows + 63) / 64;
+    s.n2 = (rows + 4095) / 4096;
+    uint32_t off = 0;
+    const uint32_t sizes[9] = {256,                       // header
+                               ((rows + 1) / 2) * 4,      // row counts, two uint16 per word
+                               s.n1 * 4,                  // sums over 64 rows
+                               s.n2 * 4,                  // sums over 4096 rows
+                               kRing * 4, kBatch * 4, kEdges * 16, kSlots * 20, kHash * 8};
+    uint32_t at[9];
+    for (int i = 0; i < 9; ++i) {
+        at[i] = off;
+        off += (sizes[i] + 15) & ~15u;
+    }
+    s.hdr = at[0];
+    s.cnt0 = at[1];
+    s.cnt1 = at[2];
+    s.cnt2 = at[3];
+    s.ring = at[4];
+    s.banc = at[5];
+    s.edges = at[6];
+    s.slots = at[7];
+    s.hash = at[8];
+    s.total = off;
+    return s;
+}
+
+struct KernelArgs {
+    const DevDesc *descs;
+    uint32_t n;
+    uint32_t tile;
+    uint32_t *queue;
+    uint8_t *slabs;
+    uint64_t slab_stride;
+    DevResult *results;
+};
+
+// Schedules ("tiles"): waves that share the select/clear of one sample; one
+// more wave per workgroup labels clusters.
+constexpr int kNumTiles = 5;
+constexpr int kTileWaves[kNumTiles] = {1, 2, 3, 7, 15};   // + 1 labelling wave: <= 1024 threads
+
+}  // namespace rsa

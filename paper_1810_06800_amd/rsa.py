@@ -1,0 +1,247 @@
+"""ctypes binding of the C ABI in ``include/rsa.h`` (argument marshalling only).
+
+Every step of the method runs in the HIP library; this module converts
+descriptors and results, hands the library torch's current HIP stream and,
+by default, torch's caching allocator for device memory.  It raises
+``RuntimeError`` when the library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librsa_hip.so")
+
+RSA_OK, RSA_EINVAL, RSA_ENOMEM, RSA_EDEVICE, RSA_ENOTREADY, RSA_EBUSY, RSA_ENOTFOUND = (
+    0, -1, -2, -3, -4, -5, -6)
+FLAG_H_ONLY = 1
+FLAG_TRACK_CLUSTERS = 2
+OPT_MODE, OPT_TILE, OPT_GRAPH, OPT_SLOTS = 1, 2, 3, 4
+MODE_BATCHED, MODE_PLAIN = 0, 1
+
+# Symbols declared in include/rsa.h.
+EXPORTS = ("rsa_create", "rsa_footprint_bytes", "rsa_run_batch", "rsa_results",
+           "rsa_batch_elapsed_ms", "rsa_destroy", "rsa_strerror", "rsa_last_error",
+           "rsa_set_option", "rsa_get_option", "rsa_num_tiles", "rsa_tile_for_shape")
+
+
+class Sample(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("k", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("sample", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("n_jam", ctypes.c_int64), ("n_wrap_x", ctypes.c_int64),
+                ("n_wrap_y", ctypes.c_int64), ("n_wrap_any", ctypes.c_int64),
+                ("occ_hash", ctypes.c_uint64), ("seq_hash", ctypes.c_uint64),
+                ("n_clusters_jam", ctypes.c_int32), ("n_nonwrapping_jam", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("alg_bytes", ctypes.c_uint64), ("wchg_words", ctypes.c_uint64)]
+
+
+RESULT_FIELDS = [name for name, _ in Result._fields_]
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class RsaError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        self.code = code
+        super().__init__(f"rsa error {code} ({strerror(code)}){': ' + msg if msg else ''}")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``librsa_hip.so``; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1810_06800_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    L.rsa_create.argtypes = [ctypes.POINTER(vp), i32, u64, ctypes.POINTER(Allocator)]
+    L.rsa_create.restype = i32
+    L.rsa_footprint_bytes.argtypes = [u32, u32]
+    L.rsa_footprint_bytes.restype = ctypes.c_size_t
+    L.rsa_run_batch.argtypes = [vp, ctypes.POINTER(Sample), u32, vp, ctypes.POINTER(u64)]
+    L.rsa_run_batch.restype = i32
+    L.rsa_results.argtypes = [vp, u64, ctypes.POINTER(Result), u32, i32]
+    L.rsa_results.restype = i32
+    L.rsa_batch_elapsed_ms.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_float)]
+    L.rsa_batch_elapsed_ms.restype = i32
+    L.rsa_destroy.argtypes = [vp]
+    L.rsa_destroy.restype = None
+    L.rsa_strerror.argtypes = [i32]
+    L.rsa_strerror.restype = ctypes.c_char_p
+    L.rsa_last_error.argtypes = [vp]
+    L.rsa_last_error.restype = ctypes.c_char_p
+    L.rsa_set_option.argtypes = [vp, i32, ctypes.c_int64]
+    L.rsa_set_option.restype = i32
+    L.rsa_get_option.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
+    L.rsa_get_option.restype = i32
+    L.rsa_num_tiles.argtypes = []
+    L.rsa_num_tiles.restype = i32
+    L.rsa_tile_for_shape.argtypes = [u32, u32]
+    L.rsa_tile_for_shape.restype = i32
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return lib().rsa_strerror(code).decode()
+
+
+def footprint_bytes(L: int, k: int) -> int:
+    return lib().rsa_footprint_bytes(L, k)
+
+
+def num_tiles() -> int:
+    return lib().rsa_num_tiles()
+
+
+def tile_for_shape(L: int, k: int) -> int:
+    return lib().rsa_tile_for_shape(L, k)
+
+
+def make_samples(descs: Iterable[Sequence[int]]):
+    """(L, k, seed, sample[, flags]) tuples -> a ctypes array of rsa_sample_t."""
+    descs = [tuple(int(v) for v in d) for d in descs]
+    arr = (Sample * max(len(descs), 1))()
+    for i, d in enumerate(descs):
+        L, k, seed, sample = d[:4]
+        flags = d[4] if len(d) > 4 else 0
+        arr[i] = Sample(L, k, seed & (2**64 - 1), sample, flags)
+    return arr, len(descs)
+
+
+def _torch_allocator(device: int):
+    """rsa_allocator_t backed by torch's caching allocator on `device`."""
+    import torch
+
+    def alloc(nbytes, _user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+        except Exception:  # out of memory: the library reports RSA_ENOMEM
+            return None
+
+    def free(ptr, _nbytes, _user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    fa, ff = ALLOC_FN(alloc), FREE_FN(free)
+    return Allocator(fa, ff, None), (fa, ff)
+
+
+class Context:
+    """An rsa_ctx on one device.  ``allocator='torch'`` (default) takes device
+    memory from torch's caching allocator; ``'hip'`` lets the library call
+    hipMalloc.  Work goes to torch's current stream unless a stream is given."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, allocator: str = "torch"):
+        self._lib = lib()
+        self.device = device
+        self._keep = None
+        alloc_ptr = None
+        if allocator == "torch":
+            import torch
+
+            torch.cuda.init()
+            alloc, self._keep = _torch_allocator(device)
+            self._alloc = alloc
+            alloc_ptr = ctypes.byref(alloc)
+        elif allocator != "hip":
+            raise ValueError("allocator must be 'torch' or 'hip'")
+        handle = ctypes.c_void_p()
+        rc = self._lib.rsa_create(ctypes.byref(handle), device, budget_bytes, alloc_ptr)
+        if rc != RSA_OK:
+            raise RsaError(rc, "rsa_create")
+        self._h = handle
+
+    # -- options
+    def set_option(self, option: int, value: int) -> None:
+        rc = self._lib.rsa_set_option(self._h, option, value)
+        if rc != RSA_OK:
+            raise RsaError(rc, self.last_error())
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int64()
+        rc = self._lib.rsa_get_option(self._h, option, ctypes.byref(v))
+        if rc != RSA_OK:
+            raise RsaError(rc, self.last_error())
+        return v.value
+
+    def last_error(self) -> str:
+        return self._lib.rsa_last_error(self._h).decode()
+
+    # -- batches
+    def run_batch(self, descs, stream=None) -> tuple[int, int]:
+        """Enqueue samples; returns (batch_id, n)."""
+        arr, n = make_samples(descs)
+        if stream is None:
+            import torch
+
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        bid = ctypes.c_uint64()
+        rc = self._lib.rsa_run_batch(self._h, arr, n, ctypes.c_void_p(stream), ctypes.byref(bid))
+        if rc != RSA_OK:
+            raise RsaError(rc, self.last_error())
+        return bid.value, n
+
+    def elapsed_ms(self, batch) -> float:
+        bid = batch[0] if isinstance(batch, tuple) else batch
+        ms = ctypes.c_float()
+        rc = self._lib.rsa_batch_elapsed_ms(self._h, bid, ctypes.byref(ms))
+        if rc != RSA_OK:
+            raise RsaError(rc, self.last_error())
+        return float(ms.value)
+
+    def results(self, batch, wait: bool = True):
+        """Results of a batch as a list of dicts (None if not ready and
+        wait=False)."""
+        bid, n = batch
+        out = (Result * max(n, 1))()
+        rc = self._lib.rsa_results(self._h, bid, out, n, 1 if wait else 0)
+        if rc == RSA_ENOTREADY:
+            return None
+        if rc != RSA_OK:
+            raise RsaError(rc, self.last_error())
+        return [{f: getattr(out[i], f) for f in RESULT_FIELDS} for i in range(n)]
+
+    def run(self, descs, stream=None):
+        return self.results(self.run_batch(descs, stream))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.rsa_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def results_array(results: list[dict]) -> np.ndarray:
+    """Results as a numpy structured array (for vectorised checks)."""
+    dt = np.dtype([(f, np.int64 if f not in ("occ_hash", "seq_hash", "alg_bytes", "wchg_words")
+                    else np.uint64) for f in RESULT_FIELDS])
+    return np.array([tuple(r[f] for f in RESULT_FIELDS) for r in results], dtype=dt)

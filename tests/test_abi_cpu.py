@@ -1,0 +1,78 @@
+"""The C-ABI library loads on the CPU and exports what include/rsa.h declares.
+
+No compute call is made: only entry points that need no device.
+"""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rsa.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsa_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def rsa():
+    from paper_1810_06800_amd import rsa as mod
+
+    if not os.path.exists(mod.LIB_PATH):
+        pytest.fail("librsa_hip.so not built: run __graft_entry__.build()")
+    return mod
+
+
+def test_every_declared_symbol_is_exported(rsa):
+    lib = rsa.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(rsa.EXPORTS)
+
+
+def test_footprint_matches_layout(rsa):
+    # two bitmaps of L*ceil(L/64) words, int32 map, 20 B per k-mer record,
+    # every area 256-byte aligned
+    def expect(L, k):
+        a = lambda v: (v + 255) // 256 * 256
+        wd = (L + 63) // 64
+        cap = L * L // k + 1
+        return a(L * wd * 8) * 2 + a(4 * L * L) + a(16 * cap) + a(4 * cap)
+
+    for L, k in [(1, 1), (5, 3), (64, 8), (1024, 64), (16384, 1024), (32768, 4096)]:
+        assert rsa.footprint_bytes(L, k) == expect(L, k)
+    assert rsa.footprint_bytes(1024, 64) < 5 * 2**20
+    assert 4.2 * 2**30 < rsa.footprint_bytes(32768, 4096) < 4.4 * 2**30
+    for L, k in [(0, 0), (4, 5), (32769, 8), (8, 0)]:
+        assert rsa.footprint_bytes(L, k) == 0
+
+
+def test_strerror_and_tiles(rsa):
+    for code in range(-6, 1):
+        assert rsa.strerror(code) and rsa.strerror(code) != "unknown status"
+    assert rsa.strerror(-99) == "unknown status"
+    n = rsa.num_tiles()
+    assert n >= 1
+    for L, k in [(64, 8), (1024, 64), (4096, 256), (16384, 1024), (32768, 4096)]:
+        assert 0 <= rsa.tile_for_shape(L, k) < n
+    assert rsa.tile_for_shape(4, 5) == rsa.RSA_EINVAL
+
+
+def test_workloads_shapes():
+    from paper_1810_06800_amd import workloads as w
+
+    assert len(w.plain_small()) == 256 and all(d[:2] == (64, 8) for d in w.plain_small())
+    assert len(w.plain_scale()) == 1024 and {d[2] for d in w.plain_scale()} == set(range(1024))
+    mixed = w.mixed_batch()
+    assert len(mixed) == 512 and {d[:2] for d in mixed} == set(w.MIXED_SHAPES)
+    assert mixed == w.mixed_batch()  # seeded
+    assert len(w.large_16k()) == 32 and len(w.large_32k()) == 8
+    tr = w.serving_trace(200)
+    assert all(2 <= r["k"] <= r["L"] // 8 and 1 <= r["n"] <= 64 for r in tr)
+    gaps = [b["arrival_s"] - a["arrival_s"] for a, b in zip(tr, tr[1:])]
+    assert 0.003 < sum(gaps) / len(gaps) < 0.008

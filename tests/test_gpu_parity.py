@@ -1,0 +1,161 @@
+"""GPU parity: the HIP library, called through the C ABI, against the oracle.
+
+Every field is an integer (counts, hashes, byte counts), so the bar is
+bit-exact equality, sample by sample.  Shapes: every tiny torus (seams,
+k = L, L <= 2), random shapes with ragged L % 64, H-only rings, the cluster
+census, and the benchmark workloads at full size in the launch configuration
+the benchmark times (all samples on the GPU, the oracle on all or a seeded
+subset of them).
+"""
+import os
+import random
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("n_jam", "n_wrap_x", "n_wrap_y", "n_wrap_any", "occ_hash", "seq_hash",
+          "alg_bytes", "wchg_words")
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_1810_06800_amd import rsa
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = rsa.Context(0)
+    yield c
+    c.close()
+
+
+def check(descs, got, want, census=False):
+    bad = []
+    for d, g, w in zip(descs, got, want):
+        assert w["status"] == 0, (d, w["status"])
+        if g["status"] != 0:
+            bad.append((d, "status", g["status"], 0))
+            continue
+        for f in FIELDS:
+            if g[f] != w[f]:
+                bad.append((d, f, g[f], w[f]))
+                break
+        if census and len(d) > 4 and d[4] & 2:
+            if (g["n_clusters_jam"], g["n_nonwrapping_jam"]) != (w["n_clusters_jam"], 0):
+                bad.append((d, "census", g["n_clusters_jam"], w["n_clusters_jam"]))
+    assert not bad, f"{len(bad)} mismatches, first: {bad[:5]}"
+
+
+def test_tiny_tori_every_k(ctx, orc):
+    descs = []
+    for L in range(1, 13):
+        for k in range(1, L + 1):
+            for seed, sample in ((0, 0), (0xDEADBEEFCAFEF00D, 12345)):
+                descs.append((L, k, seed, sample, 2 if (L + k) % 2 else 0))
+    _log(f"tiny tori: {len(descs)} samples")
+    got = ctx.run(descs)
+    check(descs, got, orc.run_many(descs), census=True)
+
+
+def test_random_shapes(ctx, orc):
+    rng = random.Random(99)
+    descs = []
+    for _ in range(200):
+        L = rng.randint(2, 300)
+        k = rng.randint(1, max(1, min(L, rng.choice([2, 4, 8, 16, 40, L]))))
+        descs.append((L, k, rng.getrandbits(64), rng.getrandbits(32), rng.choice([0, 2])))
+    _log(f"random shapes: {len(descs)} samples")
+    got = ctx.run(descs)
+    check(descs, got, orc.run_many(descs), census=True)
+
+
+def test_h_only_rings(ctx, orc):
+    descs = [(L, k, 5, s, 1) for L, k in [(64, 2), (48, 8), (33, 16), (130, 3)] for s in range(8)]
+    got = ctx.run(descs)
+    check(descs, got, orc.run_many(descs))
+
+
+def test_plain_small_workload(ctx, orc):
+    from paper_1810_06800_amd import workloads
+
+    descs = workloads.plain_small()
+    _log("plain_small: 256 x (64, 8)")
+    got = ctx.run(descs)
+    check(descs, got, orc.run_many(descs))
+
+
+def test_plain_scale_workload_full(ctx, orc):
+    """L = 1024, k = 64, seeds 0..1023: the benchmark's batch, all checked."""
+    from paper_1810_06800_amd import workloads
+
+    descs = workloads.plain_scale()
+    _log("plain_scale: 1024 x (1024, 64)")
+    got = ctx.run(descs)
+    want = orc.run_many(descs, threads=min(16, os.cpu_count() or 1))
+    check(descs, got, want)
+
+
+def test_tiles_and_modes_agree(ctx, orc):
+    """A sample's result does not depend on the schedule, the batch it sits in,
+    or plain vs batched launches."""
+    from paper_1810_06800_amd import rsa
+
+    descs = [(64, 8, 1, s, 0) for s in range(4)] + [(200, 20, 3, 1, 2), (96, 96, 2, 0, 0),
+                                                     (300, 7, 8, 2, 0), (130, 65, 4, 4, 2)]
+    want = orc.run_many(descs)
+    try:
+        for tile in range(rsa.num_tiles()):
+            ctx.set_option(rsa.OPT_TILE, tile)
+            check(descs, ctx.run(descs), want, census=True)
+        ctx.set_option(rsa.OPT_TILE, -1)
+        ctx.set_option(rsa.OPT_MODE, rsa.MODE_PLAIN)
+        check(descs, ctx.run(descs), want, census=True)
+        ctx.set_option(rsa.OPT_MODE, rsa.MODE_BATCHED)
+        ctx.set_option(rsa.OPT_GRAPH, 0)
+        check(descs, ctx.run(descs), want, census=True)
+        ctx.set_option(rsa.OPT_GRAPH, 1)
+        ctx.set_option(rsa.OPT_SLOTS, 3)
+        mixed = descs + [(128, 4, 9, s, 0) for s in range(20)]
+        got = ctx.run(mixed)
+        check(descs, got[: len(descs)], want, census=True)
+        # alone vs in the mix
+        for i in (0, 5):
+            check([descs[i]], ctx.run([descs[i]]), [want[i]], census=True)
+    finally:
+        ctx.set_option(rsa.OPT_TILE, -1)
+        ctx.set_option(rsa.OPT_MODE, rsa.MODE_BATCHED)
+        ctx.set_option(rsa.OPT_GRAPH, 1)
+        ctx.set_option(rsa.OPT_SLOTS, 0)
+
+
+def test_graph_replays_repeat(ctx, orc):
+    """The same batch replayed from the cached graph gives the same results,
+    with other work and synchronisations in between."""
+    import torch
+
+    descs = [(100, 10, 11, s, 0) for s in range(12)]
+    want = orc.run_many(descs)
+    for rep in range(4):
+        check(descs, ctx.run(descs), want)
+        x = torch.ones(1 << 20, device="cuda")
+        torch.cuda.synchronize()
+        assert float(x.sum()) == float(1 << 20)
+
+
+def test_invalid_descriptors_rejected(ctx):
+    from paper_1810_06800_amd import rsa
+
+    for bad in [(4, 5, 0, 0, 0), (0, 0, 0, 0, 0), (32769, 8, 0, 0, 0), (16, 4, 0, 0, 8)]:
+        with pytest.raises(rsa.RsaError) as e:
+            ctx.run_batch([bad])
+        assert e.value.code == rsa.RSA_EINVAL
+    # the context still works afterwards
+    assert ctx.run([(8, 2, 0, 0, 0)])[0]["status"] == 0
+    assert ctx.run([]) == []
