@@ -154,6 +154,19 @@ int rsa_results(rsa_ctx *ctx, uint64_t batch_id, rsa_result_t *out, uint32_t n, 
  * unknown id. */
 int rsa_batch_elapsed_ms(rsa_ctx *ctx, uint64_t batch_id, float *ms);
 
+/* Diagnostic: per-sample phase counters of a batch run with RSA_OPT_PROFILE.
+ * out receives n * (*slots) uint64 values, sample-major, in descriptor order;
+ * *slots and *clock_khz (the tick rate) are written even on failure.  Slot
+ * order: init, select-chain total / ring wait / select / clear, labelling
+ * total / idle / map / gather / resolve / merge / write-back (ticks), then
+ * labelling batches, edges, flushes, steps and rows read ahead correctly
+ * (counts), then the select wave's clear split into issue + read-ahead and
+ * wait + update (ticks).  Blocks until the
+ * kernels are done; valid until rsa_results.  RSA_EINVAL if the batch was
+ * not profiled or n differs from its size. */
+int rsa_batch_profile(rsa_ctx *ctx, uint64_t batch_id, uint64_t *out, uint32_t n,
+                      uint32_t *slots, uint32_t *clock_khz);
+
 /* Wait for all work of the context, free every allocation and the context.
  * NULL is ignored. */
 void rsa_destroy(rsa_ctx *ctx);
@@ -177,16 +190,26 @@ const char *rsa_last_error(rsa_ctx *ctx);
  *                  hipGraph once per shape signature and replayed; 0 = direct
  *   RSA_OPT_SLOTS  0 (default) = as many resident workgroups as fit, else
  *                  an upper bound on them
+ *   RSA_OPT_PROFILE 0 (default); 1 = later batches record per-sample phase
+ *                  counters (device wall-clock ticks), read by
+ *                  rsa_batch_profile; results are unchanged
  * Unknown options or values: RSA_EINVAL. */
-enum rsa_option { RSA_OPT_MODE = 1, RSA_OPT_TILE = 2, RSA_OPT_GRAPH = 3, RSA_OPT_SLOTS = 4 };
+enum rsa_option { RSA_OPT_MODE = 1, RSA_OPT_TILE = 2, RSA_OPT_GRAPH = 3, RSA_OPT_SLOTS = 4,
+                  RSA_OPT_PROFILE = 5 };
 enum rsa_mode { RSA_MODE_BATCHED = 0, RSA_MODE_PLAIN = 1 };
 int rsa_set_option(rsa_ctx *ctx, int option, int64_t value);
 int rsa_get_option(rsa_ctx *ctx, int option, int64_t *value);
 
-/* Number of schedules ("tiles") the library implements, and the one the
- * autotune table picks for a shape. */
+/* Schedules ("tiles").  A tile fixes the waves that share one sample's
+ * select/clear (one more wave labels clusters), the height of the 128-byte
+ * bitmap tiles (1..16 rows of 16..1 words) and of the 128-byte site-map tiles
+ * (1..32 rows of 32..1 sites).  Results never depend on the tile.
+ * rsa_num_tiles: how many exist; rsa_tile_for_shape: the one the autotune
+ * table picks for (L, k) (RSA_EINVAL for an invalid shape); rsa_tile_shape:
+ * decode a tile id (RSA_EINVAL if out of range; NULL outputs are skipped). */
 int rsa_num_tiles(void);
 int rsa_tile_for_shape(uint32_t L, uint32_t k);
+int rsa_tile_shape(int tile, int *waves, int *bitmap_tile_rows, int *map_tile_rows);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@
 #include "rsa_device.h"
 
 namespace rsa {
-extern const void *kPersistentKernels[kNumTiles];
+extern const void *kPersistentKernels[kNumWaveTiles][2];
 extern const void *kResetKernel;
 }  // namespace rsa
 
@@ -35,7 +35,8 @@ namespace {
 constexpr int kPlainStreams = 4;
 
 struct Group {
-    int tile;
+    int waves;               // index into kTileWaves (the kernel instantiation)
+    int wide;                // rows of more than 64 words (L > 4096)
     uint32_t first, count;   // range in the planned descriptor array
     uint32_t grid;
     uint32_t lds;
@@ -57,6 +58,7 @@ struct Batch {
     hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_done = nullptr;
     std::vector<Group> groups;
     int mode = RSA_MODE_BATCHED;
+    unsigned long long *d_prof = nullptr;   // inside mem, or null
 };
 
 struct GraphEntry {
@@ -80,7 +82,8 @@ struct rsa_ctx {
     std::map<uint64_t, Batch *> batches;
     std::vector<Block> pool;   // free device blocks
     std::vector<GraphEntry> graphs;
-    int64_t opt_mode = RSA_MODE_BATCHED, opt_tile = -1, opt_graph = 1, opt_slots = 0;
+    int64_t opt_mode = RSA_MODE_BATCHED, opt_tile = -1, opt_graph = 1, opt_slots = 0, opt_prof = 0;
+    int clock_khz = 0;
     hipStream_t plain[kPlainStreams] = {};
     hipEvent_t fork = nullptr, join[kPlainStreams] = {};
     int resident[kNumTiles][4] = {};   // cached occupancy per tile and LDS class
@@ -116,15 +119,13 @@ bool valid_sample(const rsa_sample_t &s)
 }
 
 // Schedule heuristic: waves that share the select/clear of one sample grow
-// with the k x k block a deposit clears.
+// with the k x k block a deposit clears; 8-row bitmap tiles and 8-row map
+// tiles keep a k-row block to about k/8 cache lines.
 int default_tile(uint32_t L, uint32_t k)
 {
     (void)L;
-    if (k <= 64) return 0;
-    if (k <= 128) return 1;
-    if (k <= 256) return 2;
-    if (k <= 1024) return 3;
-    return 4;
+    int waves = k <= 64 ? 0 : (k <= 128 ? 1 : (k <= 256 ? 2 : (k <= 1024 ? 3 : 4)));
+    return make_tile(waves, 3, 3);
 }
 
 // Relative cost of a sample: deposits (about 0.7 L^2 / k) times the words a
@@ -133,7 +134,7 @@ double sample_cost(uint32_t L, uint32_t k, int tile)
 {
     double steps = 0.7 * (double)L * L / k;
     double words = (double)k * ((double)k / 64.0 + 1.0);
-    return steps * (8.0 + words / (64.0 * kTileWaves[tile]));
+    return steps * (8.0 + words / (64.0 * kTileWaves[tile_waves(tile)]));
 }
 
 void *dev_alloc(rsa_ctx *c, size_t bytes)
@@ -197,18 +198,18 @@ void give_block(rsa_ctx *c, Block b)
     if (b.ptr) c->pool.push_back(b);
 }
 
-int resident_blocks(rsa_ctx *c, int tile, uint32_t lds)
+int resident_blocks(rsa_ctx *c, int tile, int wide, uint32_t lds)
 {
     int nb = 0;
     int threads = 64 * (kTileWaves[tile] + 1);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kPersistentKernels[tile], threads, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kPersistentKernels[tile][wide], threads, lds) !=
             hipSuccess ||
         nb < 1)
         nb = 1;
     return nb * c->cus;
 }
 
-DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out)
+DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile)
 {
     DevDesc d;
     std::memset(&d, 0, sizeof(d));
@@ -222,6 +223,17 @@ DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out)
     d.fL = make_fastdiv(s.L);
     d.fk = make_fastdiv(s.k);
     d.fC = make_fastdiv(2 * s.k + 2);
+    d.fwd = make_fastdiv(d.wd);
+    d.fwp = make_fastdiv(padded_words(s.L));
+    d.tile = (uint32_t)tile;
+    d.lg_tr = (uint32_t)tile_lg_tr(tile);
+    d.lg_mr = (uint32_t)tile_lg_mr(tile);
+    // read-ahead window: as many rows as two (eight for wide rows) words per
+    // lane hold, a power of two, at most 16
+    uint32_t budget = 64u * (s.L > 4096 ? 8u : 2u) / d.wd;
+    uint32_t nr = 1;
+    while (nr * 2 <= budget && nr * 2 <= 16) nr *= 2;
+    d.spec_rows = nr;
     return d;
 }
 
@@ -282,6 +294,15 @@ int rsa_tile_for_shape(uint32_t L, uint32_t k)
     return default_tile(L, k);
 }
 
+int rsa_tile_shape(int tile, int *waves, int *bitmap_tile_rows, int *map_tile_rows)
+{
+    if (tile < 0 || tile >= kNumTiles) return RSA_EINVAL;
+    if (waves) *waves = kTileWaves[tile_waves(tile)];
+    if (bitmap_tile_rows) *bitmap_tile_rows = 1 << tile_lg_tr(tile);
+    if (map_tile_rows) *map_tile_rows = 1 << tile_lg_mr(tile);
+    return RSA_OK;
+}
+
 int rsa_create(rsa_ctx **out, int device, uint64_t hbm_budget_bytes, const rsa_allocator_t *alloc)
 {
     if (!out) return RSA_EINVAL;
@@ -302,13 +323,17 @@ int rsa_create(rsa_ctx **out, int device, uint64_t hbm_budget_bytes, const rsa_a
         return RSA_EDEVICE;
     }
     c->cus = p.multiProcessorCount;
+    if (hipDeviceGetAttribute(&c->clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess)
+        c->clock_khz = 0;
     c->lds_max = p.sharedMemPerBlock;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)p.totalGlobalMem);
-    for (int t = 0; t < kNumTiles; ++t) {
-        if (hipFuncSetAttribute(kPersistentKernels[t], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(c->lds_max - 64)) != hipSuccess) {
-            delete c;
-            return RSA_EDEVICE;
+    for (int t = 0; t < kNumWaveTiles; ++t) {
+        for (int w = 0; w < 2; ++w) {
+            if (hipFuncSetAttribute(kPersistentKernels[t][w], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(c->lds_max - 64)) != hipSuccess) {
+                delete c;
+                return RSA_EDEVICE;
+            }
         }
     }
     for (int i = 0; i < kPlainStreams; ++i) {
@@ -346,6 +371,10 @@ int rsa_set_option(rsa_ctx *c, int option, int64_t value)
         if (value < 0) return fail(c, RSA_EINVAL, "bad slot bound");
         c->opt_slots = value;
         return RSA_OK;
+    case RSA_OPT_PROFILE:
+        if (value != 0 && value != 1) return fail(c, RSA_EINVAL, "bad profile flag");
+        c->opt_prof = value;
+        return RSA_OK;
     default: return fail(c, RSA_EINVAL, "unknown option");
     }
 }
@@ -358,6 +387,7 @@ int rsa_get_option(rsa_ctx *c, int option, int64_t *value)
     case RSA_OPT_TILE: *value = c->opt_tile; return RSA_OK;
     case RSA_OPT_GRAPH: *value = c->opt_graph; return RSA_OK;
     case RSA_OPT_SLOTS: *value = c->opt_slots; return RSA_OK;
+    case RSA_OPT_PROFILE: *value = c->opt_prof; return RSA_OK;
     default: return fail(c, RSA_EINVAL, "unknown option");
     }
 }
@@ -377,29 +407,35 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     b->mode = (int)c->opt_mode;
 
     // ---- plan: group by tile, longest samples first inside a group
-    std::vector<int> tiles(n);
-    for (uint32_t i = 0; i < n; ++i)
+    // group key: wave count * 2 + (rows wider than 64 words)
+    std::vector<int> tiles(n), keys(n);
+    for (uint32_t i = 0; i < n; ++i) {
         tiles[i] = c->opt_tile >= 0 ? (int)c->opt_tile : default_tile(s[i].L, s[i].k);
+        keys[i] = tile_waves(tiles[i]) * 2 + (s[i].L > 4096 ? 1 : 0);
+    }
     std::vector<uint32_t> order(n);
     for (uint32_t i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t bb) {
-        if (tiles[a] != tiles[bb]) return tiles[a] > tiles[bb];
+        if (keys[a] != keys[bb]) return keys[a] > keys[bb];
         return sample_cost(s[a].L, s[a].k, tiles[a]) > sample_cost(s[bb].L, s[bb].k, tiles[bb]);
     });
     size_t total = 0;
     const size_t desc_bytes = align256((size_t)std::max<uint32_t>(n, 1) * sizeof(DevDesc));
     const size_t res_bytes = align256((size_t)std::max<uint32_t>(n, 1) * sizeof(DevResult));
-    const size_t queue_count = b->mode == RSA_MODE_PLAIN ? std::max<uint32_t>(n, 1) : kNumTiles;
+    const size_t queue_count = b->mode == RSA_MODE_PLAIN ? std::max<uint32_t>(n, 1) : 2 * kNumTiles;
     const size_t queue_bytes = align256(queue_count * 4);
-    total = desc_bytes + res_bytes + queue_bytes;
+    const size_t prof_words = c->opt_prof ? (size_t)std::max<uint32_t>(n, 1) * kProfSlots : 0;
+    const size_t prof_bytes = align256(prof_words * 8);
+    total = desc_bytes + res_bytes + queue_bytes + prof_bytes;
     for (uint32_t i = 0; i < n;) {
         Group g;
-        g.tile = tiles[order[i]];
+        g.waves = keys[order[i]] >> 1;
+        g.wide = keys[order[i]] & 1;
         g.first = i;
         uint32_t j = i;
         size_t stride = 0;
         uint32_t lds = 0;
-        while (j < n && tiles[order[j]] == g.tile) {
+        while (j < n && keys[order[j]] == keys[order[i]]) {
             stride = std::max(stride, slab_layout(s[order[j]].L, s[order[j]].k).total);
             lds = std::max(lds, lds_layout(s[order[j]].L).total);
             ++j;
@@ -412,7 +448,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         if (b->mode == RSA_MODE_PLAIN) {
             grid = kPlainStreams;   // one slab per stream: samples on a stream run in order
         } else {
-            grid = std::min<uint32_t>(g.count, (uint32_t)resident_blocks(c, g.tile, lds));
+            grid = std::min<uint32_t>(g.count, (uint32_t)resident_blocks(c, g.waves, g.wide, lds));
             if (c->opt_slots > 0) grid = std::min<uint32_t>(grid, (uint32_t)c->opt_slots);
         }
         g.grid = grid;
@@ -442,6 +478,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     DevDesc *d_desc = (DevDesc *)base;
     DevResult *d_res = (DevResult *)(base + desc_bytes);
     uint32_t *d_queue = (uint32_t *)(base + desc_bytes + res_bytes);
+    b->d_prof = prof_words ? (unsigned long long *)(base + desc_bytes + res_bytes + queue_bytes) : nullptr;
 
     // ---- descriptors (pinned staging), copied before the call returns
     if (hipHostMalloc((void **)&b->h_desc, desc_bytes, hipHostMallocDefault) != hipSuccess ||
@@ -449,7 +486,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         destroy_batch(c, b.release());
         return fail(c, RSA_ENOMEM, "pinned host allocation failed");
     }
-    for (uint32_t i = 0; i < n; ++i) b->h_desc[i] = make_dev_desc(s[order[i]], order[i]);
+    for (uint32_t i = 0; i < n; ++i) b->h_desc[i] = make_dev_desc(s[order[i]], order[i], tiles[order[i]]);
     HIP_TRY(c, hipEventCreate(&b->ev_start));
     HIP_TRY(c, hipEventCreate(&b->ev_end));
     HIP_TRY(c, hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
@@ -458,17 +495,25 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
                                   hipMemcpyHostToDevice, stream));
 
     // ---- launches
+    if (b->d_prof) {
+        // zero the counters with the fill kernel (outside any graph)
+        uint32_t words = (uint32_t)(prof_words * 2);
+        uint32_t *pw = (uint32_t *)b->d_prof;
+        void *zargs[] = {&pw, &words};
+        HIP_TRY(c, hipLaunchKernel(kResetKernel, dim3((words + 255) / 256), dim3(256), zargs, 0, stream));
+    }
     HIP_TRY(c, hipEventRecord(b->ev_start, stream));
     std::vector<KernelArgs> args;
     for (auto &g : b->groups) {
         KernelArgs a;
         a.descs = d_desc + g.first;
         a.n = g.count;
-        a.tile = (uint32_t)g.tile;
-        a.queue = d_queue + g.tile;
+        a.tile = (uint32_t)g.waves;
+        a.queue = d_queue + g.waves * 2 + g.wide;
         a.slabs = base + g.slab_off;
         a.slab_stride = g.stride;
         a.results = d_res;
+        a.prof = b->d_prof;
         args.push_back(a);
     }
     if (n == 0) {
@@ -483,19 +528,20 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         for (int i = 0; i < kPlainStreams; ++i) HIP_TRY(c, hipStreamWaitEvent(c->plain[i], c->fork, 0));
         uint32_t idx = 0;
         for (auto &g : b->groups) {
-            int threads = 64 * (kTileWaves[g.tile] + 1);
+            int threads = 64 * (kTileWaves[g.waves] + 1);
             for (uint32_t j = 0; j < g.count; ++j, ++idx) {
                 int si = (int)(idx % kPlainStreams);
                 KernelArgs a;
                 a.descs = d_desc + g.first + j;
                 a.n = 1;
-                a.tile = (uint32_t)g.tile;
+                a.tile = (uint32_t)g.waves;
                 a.queue = d_queue + g.first + j;
                 a.slabs = base + g.slab_off + (size_t)si * g.stride;
                 a.slab_stride = 0;
                 a.results = d_res;
+                a.prof = b->d_prof;
                 void *kargs[] = {&a};
-                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.tile], dim3(1), dim3(threads), kargs,
+                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.waves][g.wide], dim3(1), dim3(threads), kargs,
                                            g.lds, c->plain[si]));
             }
         }
@@ -510,11 +556,11 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         for (size_t i = 0; i < args.size(); ++i) {
             const Group &g = b->groups[i];
             char buf[64];
-            std::snprintf(buf, sizeof(buf), "%d:%u:%u|", g.tile, g.grid, g.lds);
+            std::snprintf(buf, sizeof(buf), "%d:%d:%u:%u|", g.waves, g.wide, g.grid, g.lds);
             key += buf;
             key.append((const char *)&args[i], sizeof(KernelArgs));
         }
-        uint32_t nq = kNumTiles;
+        uint32_t nq = 2 * kNumTiles;
         if (c->opt_graph) {
             hipGraphExec_t exec = cached_graph(c, key);
             if (!exec) {
@@ -534,9 +580,9 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
                     hipKernelNodeParams kp;
                     std::memset(&kp, 0, sizeof(kp));
                     void *kargs[] = {&args[i]};
-                    kp.func = (void *)kPersistentKernels[g.tile];
+                    kp.func = (void *)kPersistentKernels[g.waves][g.wide];
                     kp.gridDim = dim3(g.grid);
-                    kp.blockDim = dim3(64 * (kTileWaves[g.tile] + 1));
+                    kp.blockDim = dim3(64 * (kTileWaves[g.waves] + 1));
                     kp.sharedMemBytes = g.lds;
                     kp.kernelParams = kargs;
                     hipGraphNode_t node;
@@ -558,8 +604,8 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
             for (size_t i = 0; i < args.size(); ++i) {
                 const Group &g = b->groups[i];
                 void *kargs[] = {&args[i]};
-                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.tile], dim3(g.grid),
-                                           dim3(64 * (kTileWaves[g.tile] + 1)), kargs, g.lds, stream));
+                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.waves][g.wide], dim3(g.grid),
+                                           dim3(64 * (kTileWaves[g.waves] + 1)), kargs, g.lds, stream));
             }
         }
     }
@@ -606,6 +652,24 @@ int rsa_batch_elapsed_ms(rsa_ctx *c, uint64_t batch_id, float *ms)
     if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
     e = hipEventElapsedTime(ms, b->ev_start, b->ev_end);
     if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+    return RSA_OK;
+}
+
+int rsa_batch_profile(rsa_ctx *c, uint64_t batch_id, uint64_t *out, uint32_t n, uint32_t *slots,
+                      uint32_t *clock_khz)
+{
+    if (!c) return RSA_EINVAL;
+    auto it = c->batches.find(batch_id);
+    if (it == c->batches.end()) return fail(c, RSA_ENOTFOUND, "unknown batch id");
+    Batch *b = it->second;
+    if (slots) *slots = kProfSlots;
+    if (clock_khz) *clock_khz = (uint32_t)c->clock_khz;
+    if (!b->d_prof) return fail(c, RSA_EINVAL, "batch was not profiled");
+    if (n != b->n || (n > 0 && !out)) return fail(c, RSA_EINVAL, "count differs from batch size");
+    hipError_t e = hipEventSynchronize(b->ev_end);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    e = hipMemcpy(out, b->d_prof, (size_t)n * kProfSlots * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy");
     return RSA_OK;
 }
 

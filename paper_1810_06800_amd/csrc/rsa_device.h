@@ -30,16 +30,28 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
     return (uint32_t)((t + n) >> f.l);
 }
 
-// One sample as the kernels see it (80 bytes).
+// Padded extents shared by every tile shape: bitmap rows of a multiple of 16
+// words and a multiple of 32 rows, a site map of a multiple of 32 in both
+// directions, so one slab size fits all tile shapes of a lattice.
+__host__ __device__ inline uint32_t padded_words(uint32_t L) { return ((L + 63) / 64 + 15) & ~15u; }
+__host__ __device__ inline uint32_t padded_side(uint32_t L) { return (L + 31) & ~31u; }
+
+// One sample as the kernels see it.
 struct DevDesc {
     uint32_t L, k;
     uint64_t seed;
     uint32_t sample, flags;
-    uint32_t out;    // index into the result array
-    uint32_t wd;     // 64-bit words per bitmap row, ceil(L/64)
-    FastDiv fL;      // division by L
-    FastDiv fk;      // division by k
-    FastDiv fC;      // division by 2k+2 (contacts per k-mer)
+    uint32_t out;      // index into the result array
+    uint32_t wd;       // 64-bit words per bitmap row, ceil(L/64)
+    uint32_t lg_tr;    // bitmap tile: 2^lg_tr rows x 2^(4-lg_tr) words (128 B)
+    uint32_t lg_mr;    // site-map tile: 2^lg_mr rows x 2^(5-lg_mr) sites (128 B)
+    uint32_t spec_rows;   // rows read ahead of each clear (power of two)
+    uint32_t tile;        // schedule id reported in the result
+    FastDiv fL;        // division by L
+    FastDiv fk;        // division by k
+    FastDiv fC;        // division by 2k+2 (contacts per k-mer)
+    FastDiv fwd;       // division by wd
+    FastDiv fwp;       // division by the padded row words
 };
 
 // Mirrors rsa_result_t of include/rsa.h (80 bytes).
@@ -52,9 +64,11 @@ struct DevResult {
 };
 
 // Per-sample device state, one slab per resident workgroup:
-//   avail[0], avail[1]  availability bitmaps of H / V placements, row-major,
-//                       L rows of wd words, bit x%64 of word x/64 = anchor x
-//   map                 int32 site -> k-mer id (deposit number), -1 = empty
+//   avail[0], avail[1]  availability bitmaps of H / V placements: bit x%64 of
+//                       word x/64 of row y is anchor (y, x); words are stored
+//                       in 128-byte tiles of 2^lg_tr rows x 2^(4-lg_tr) words
+//   map                 int32 site -> k-mer id (deposit number), -1 = empty,
+//                       in 128-byte tiles of 2^lg_mr rows x 2^(5-lg_mr) sites
 //   node                per k-mer union-find record {parent, dx, dy, meta}:
 //                       (dx, dy) = anchor minus the parent's anchor, unwrapped;
 //                       meta (roots only) = rank | wraps-in-x << 8 | -in-y << 9
@@ -68,12 +82,12 @@ __host__ __device__ inline size_t align256(size_t v) { return (v + 255) & ~size_
 __host__ __device__ inline SlabLayout slab_layout(uint32_t L, uint32_t k)
 {
     SlabLayout s;
-    size_t wd = (L + 63) / 64;
+    size_t wp = padded_words(L), lp = padded_side(L);
     size_t cap = (size_t)L * L / k + 1;
     size_t off = 0;
-    s.avail0 = off; off = align256(off + (size_t)L * wd * 8);
-    s.avail1 = off; off = align256(off + (size_t)L * wd * 8);
-    s.map = off;    off = align256(off + (size_t)L * L * 4);
+    s.avail0 = off; off = align256(off + lp * wp * 8);
+    s.avail1 = off; off = align256(off + lp * wp * 8);
+    s.map = off;    off = align256(off + lp * lp * 4);
     s.node = off;   off = align256(off + cap * 16);
     s.kmer = off;   off = align256(off + cap * 4);
     s.total = off;
@@ -131,11 +145,45 @@ struct KernelArgs {
     uint8_t *slabs;
     uint64_t slab_stride;
     DevResult *results;
+    unsigned long long *prof;   // kProfSlots counters per sample, or null
 };
 
-// Schedules ("tiles"): waves that share the select/clear of one sample; one
-// more wave per workgroup labels clusters.
-constexpr int kNumTiles = 5;
-constexpr int kTileWaves[kNumTiles] = {1, 2, 3, 7, 15};   // + 1 labelling wave: <= 1024 threads
+// Optional per-sample phase counters (device wall-clock ticks unless noted).
+enum ProfSlot {
+    kProfInit = 0,      // state initialisation
+    kProfSelTotal,      // selecting wave, first step to jamming
+    kProfSelRing,       // waiting for ring space
+    kProfSelSelect,     // draw + hierarchical select + row read
+    kProfSelClear,      // clearing blocked placements (incl. helper waits)
+    kProfLabTotal,      // labelling wave, start to exit
+    kProfLabIdle,       // waiting for placements
+    kProfLabMap,        // site-map writes of a batch
+    kProfLabGather,     // contact gathering
+    kProfLabResolve,    // global finds and slot assignment
+    kProfLabMerge,      // ordered merge in LDS
+    kProfLabWriteBack,  // local forest written back
+    kProfLabBatches,    // count
+    kProfLabEdges,      // count
+    kProfLabFlushes,    // count
+    kProfSteps,         // count
+    kProfSpecHits,      // count: next row read ahead of the clear was the right one
+    kProfSelHook,       // clear reads issued + read-ahead work (selecting wave)
+    kProfSelProcess,    // clear words back, bits cleared, counts updated
+    kProfSlots
+};
+
+// Schedules ("tiles"): waves that share the select/clear of one sample (one
+// more wave per workgroup labels clusters), the bitmap tile height and the
+// site-map tile height.  tile = waves + kNumWaveTiles * (lg_tr + 5 * lg_mr).
+constexpr int kNumWaveTiles = 5;
+constexpr int kTileWaves[kNumWaveTiles] = {1, 2, 3, 7, 15};   // + 1 labelling wave: <= 1024 threads
+constexpr int kNumTiles = kNumWaveTiles * 5 * 6;
+__host__ __device__ inline int tile_waves(int tile) { return tile % kNumWaveTiles; }
+__host__ __device__ inline int tile_lg_tr(int tile) { return (tile / kNumWaveTiles) % 5; }
+__host__ __device__ inline int tile_lg_mr(int tile) { return tile / (kNumWaveTiles * 5); }
+__host__ __device__ inline int make_tile(int waves, int lg_tr, int lg_mr)
+{
+    return waves + kNumWaveTiles * (lg_tr + 5 * lg_mr);
+}
 
 }  // namespace rsa

@@ -38,7 +38,8 @@ constexpr uint32_t kUnroll = 4;   // independent bitmap words in flight per lane
 // union-find); the sample then stops instead of reading out of bounds.
 constexpr int32_t kErrSelect = -100;
 constexpr int32_t kErrLabel = -101;
-constexpr uint32_t kMaxHops = 64;   // union by rank keeps trees below log2(L^2) levels
+constexpr uint32_t kMaxHops = 64;
+constexpr int kGather = 8;       // rounds of 64 contacts whose reads are in flight together   // union by rank keeps trees below log2(L^2) levels
 
 // ---------------------------------------------------------------------------
 // Small device helpers
@@ -67,16 +68,34 @@ __device__ __forceinline__ uint32_t lds_peek(const uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Inclusive prefix sum over the 64 lanes with DPP moves: shifts by 1, 2, 4, 8
+// inside each 16-lane row, then broadcasts of lane 15 and lane 31 into the
+// rows above (four times cheaper than LDS-crossbar shuffles).
 __device__ __forceinline__ uint32_t wave_scan(uint32_t v)
 {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        uint32_t o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
-    }
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);   // row_bcast:31
     return v;
 }
+
+// Value of a wave-uniform lane (scalar read, no LDS traffic).
+// (readlane returns int: go through uint32_t so that nothing sign-extends)
+__device__ __forceinline__ uint32_t bcast(uint32_t v, uint32_t lane)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)lane);
+}
+
+__device__ __forceinline__ uint64_t bcast64(uint64_t v, uint32_t lane)
+{
+    const uint32_t lo = bcast((uint32_t)v, lane), hi = bcast((uint32_t)(v >> 32), lane);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) { return bcast(wave_scan(v), 63); }
 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
 {
@@ -85,12 +104,7 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_sum32(uint32_t v)
-{
-#pragma unroll
-    for (uint32_t d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ uint32_t first_lane(uint64_t ballot) { return (uint32_t)(__ffsll((long long)ballot) - 1); }
 
@@ -156,11 +170,17 @@ struct Hdr {
 };
 
 struct Ctx {
+    unsigned long long *prof;   // this sample's counters, or null
     uint32_t L, k, wd, flags, sample, L2;
     uint32_t ncap;     // k-mer records in the slab, L*L/k + 1
     uint32_t k0, k1;   // Philox key
-    FastDiv fL, fk, fC;
-    uint64_t *av[2];
+    // bitmap tiles: 2^lg_tr rows x 2^lg_tw words, tpr tiles per padded row
+    uint32_t lg_tr, lg_tw, tr_m, tw_m, tpr, wp;
+    // site-map tiles: 2^lg_mr rows x 2^lg_mc sites, mtpr tiles per padded row
+    uint32_t lg_mr, lg_mc, mr_m, mc_m, mtpr, lp;
+    uint32_t spec_rows;
+    FastDiv fL, fk, fC, fwd, fwp;
+    uint64_t *av0, *av1;   // availability bitmaps of H / V placements
     int32_t *map;
     int4 *node;
     uint32_t *kmer;
@@ -174,6 +194,29 @@ struct Ctx {
     int32_t *s_dx, *s_dy;
     uint32_t *h_key, *h_val;
 };
+
+__device__ __forceinline__ uint64_t *bitmap(const Ctx &c, uint32_t o) { return o ? c.av1 : c.av0; }
+
+// Word w of bitmap row `row` inside its 128-byte tile.
+__device__ __forceinline__ size_t bm_index(const Ctx &c, uint32_t row, uint32_t w)
+{
+    return (((size_t)(row >> c.lg_tr) * c.tpr + (w >> c.lg_tw)) << 4) + ((row & c.tr_m) << c.lg_tw) +
+           (w & c.tw_m);
+}
+
+// Site (y, x) of the map inside its 128-byte tile.
+__device__ __forceinline__ size_t map_index(const Ctx &c, uint32_t y, uint32_t x)
+{
+    return (((size_t)(y >> c.lg_mr) * c.mtpr + (x >> c.lg_mc)) << 5) + ((y & c.mr_m) << c.lg_mc) +
+           (x & c.mc_m);
+}
+
+__device__ __forceinline__ uint64_t tick() { return (uint64_t)wall_clock64(); }
+
+__device__ __forceinline__ void prof_add(const Ctx &c, int slot, uint64_t v)
+{
+    if (c.prof && lane_id() == 0) atomicAdd(&c.prof[slot], (unsigned long long)v);
+}
 
 __device__ __forceinline__ uint32_t row_count(const Ctx &c, uint32_t r)
 {
@@ -209,104 +252,55 @@ __device__ __forceinline__ uint64_t col_mask(uint32_t L, uint32_t c0, uint32_t l
     return m;
 }
 
-// Make unavailable every placement of orientation o anchored in rows
-// row0 .. row0+nrows-1 (mod L) and in the cyclic columns [c0, c0+len).
-// Wave `wv` of `nwv` takes its share; each lane holds kUnroll words in flight.
-__device__ void clear_region(const Ctx &c, uint32_t o, uint32_t row0, uint32_t nrows, uint32_t c0,
-                             uint32_t len, uint32_t wv, uint32_t nwv, uint32_t &wchg)
+// A rectangle of placements to make unavailable: orientation o, anchor rows
+// row0 .. row0+nrows-1 (mod L) and anchor columns in the cyclic interval
+// [c0, c0+len).  Its items are (row, word) pairs: the columns touch words
+// a0 .. a0+nA-1 and, past the seam, words 0 .. nw-nA-1, each word once.
+struct Rect {
+    uint32_t o, row0, nrows, c0, len;
+    uint32_t a0, nA, nw;
+    uint32_t lg;      // nw <= 64: 1 << lg lanes per row; else all ones
+};
+
+__device__ __forceinline__ Rect make_rect(const Ctx &c, uint32_t o, uint32_t row0, uint32_t nrows,
+                                          uint32_t c0, uint32_t len)
 {
-    const uint32_t lane = lane_id(), L = c.L, wd = c.wd;
-    // words the column interval touches, each once: the piece [c0, ...) from
-    // word a0, then (after the seam) words 0 .. nB-1 below a0
-    uint32_t a0, nA, nB;
+    const uint32_t L = c.L;
+    Rect r;
+    r.o = o;
+    r.row0 = row0;
+    r.nrows = nrows;
+    r.c0 = c0;
+    r.len = len;
     if (len >= L) {
-        a0 = 0;
-        nA = wd;
-        nB = 0;
+        r.a0 = 0;
+        r.nA = c.wd;
+        r.nw = c.wd;
     } else {
         uint32_t end = c0 + len;
         uint32_t endA = end < L ? end : L;
-        a0 = c0 >> 6;
-        nA = ((endA - 1) >> 6) - a0 + 1;
-        nB = 0;
+        r.a0 = c0 >> 6;
+        r.nA = ((endA - 1) >> 6) - r.a0 + 1;
+        uint32_t nB = 0;
         if (end > L) {
             uint32_t b1 = (end - L - 1) >> 6;
-            nB = (b1 == a0) ? b1 : b1 + 1;
+            nB = (b1 == r.a0) ? b1 : b1 + 1;
         }
+        r.nw = r.nA + nB;
     }
-    const uint32_t nw = nA + nB;
-    uint64_t *base = c.av[o];
-    const uint32_t rowbase = o * L;
-    if (nw <= 64) {
-        uint32_t lg = nw <= 1 ? 0 : 32 - __clz(nw - 1);
-        uint32_t rows_per = 64u >> lg;
-        uint32_t wsub = lane & ((1u << lg) - 1), rsub = lane >> lg;
-        bool wact = wsub < nw;
-        uint32_t w = wsub < nA ? a0 + wsub : wsub - nA;
-        uint64_t mask = wact ? col_mask(L, c0, len, w) : 0;
-        uint32_t stride = rows_per * nwv;
-        for (uint32_t rb = wv * rows_per; rb < nrows; rb += stride * kUnroll) {
-            uint64_t old[kUnroll];
-            uint32_t row[kUnroll];
-            bool act[kUnroll];
-#pragma unroll
-            for (uint32_t u = 0; u < kUnroll; ++u) {
-                uint32_t i = rb + u * stride + rsub;
-                act[u] = wact && i < nrows;
-                uint32_t r = row0 + i;
-                r = r >= L ? r - L : r;
-                row[u] = r;
-                old[u] = act[u] ? base[(size_t)r * wd + w] : 0;
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < kUnroll; ++u) {
-                uint64_t hit = old[u] & mask;
-                if (hit) {
-                    base[(size_t)row[u] * wd + w] = old[u] & ~hit;
-                    count_sub(c, rowbase + row[u], (uint32_t)__popcll(hit));
-                    ++wchg;
-                }
-            }
-        }
-    } else {
-        for (uint32_t i = wv; i < nrows; i += nwv) {
-            uint32_t r = row0 + i;
-            r = r >= L ? r - L : r;
-            uint64_t *rowp = base + (size_t)r * wd;
-            uint32_t cleared = 0;
-            for (uint32_t j0 = 0; j0 < nw; j0 += 64 * kUnroll) {
-                uint64_t old[kUnroll], mask[kUnroll];
-                uint32_t w[kUnroll];
-#pragma unroll
-                for (uint32_t u = 0; u < kUnroll; ++u) {
-                    uint32_t j = j0 + u * 64 + lane;
-                    bool act = j < nw;
-                    w[u] = j < nA ? a0 + j : j - nA;
-                    mask[u] = act ? col_mask(L, c0, len, w[u]) : 0;
-                    old[u] = act ? rowp[w[u]] : 0;
-                }
-#pragma unroll
-                for (uint32_t u = 0; u < kUnroll; ++u) {
-                    uint64_t hit = old[u] & mask[u];
-                    if (hit) {
-                        rowp[w[u]] = old[u] & ~hit;
-                        cleared += (uint32_t)__popcll(hit);
-                        ++wchg;
-                    }
-                }
-            }
-            uint32_t tot = wave_sum32(cleared);
-            if (lane == 0 && tot) count_sub(c, rowbase + r, tot);
-        }
-    }
+    r.lg = r.nw <= 64 ? (r.nw <= 1 ? 0 : 32 - __clz(r.nw - 1)) : 0xFFFFFFFFu;
+    return r;
 }
 
 // Deposit of k-mer (o, y, x): every placement covering one of its sites stops
 // being available (Sec. II.B).  Horizontal at (y, x): H anchors in row y,
 // columns x-k+1 .. x+k-1, and V anchors in rows y-k+1 .. y, columns
 // x .. x+k-1.  Vertical: the transpose.  Runs longer than L wrap once.
-__device__ void clear_blocked(const Ctx &c, uint32_t o, uint32_t y, uint32_t x, uint32_t wv,
-                              uint32_t nwv, uint32_t &wchg)
+struct Clear {
+    Rect a, b;
+};
+
+__device__ __forceinline__ Clear make_clear(const Ctx &c, uint32_t o, uint32_t y, uint32_t x)
 {
     const uint32_t L = c.L, k = c.k;
     uint32_t strip = 2 * k - 1 < L ? 2 * k - 1 : L;
@@ -314,122 +308,391 @@ __device__ void clear_blocked(const Ctx &c, uint32_t o, uint32_t y, uint32_t x, 
     back = back >= L ? back - L : back;
     uint32_t up = y + L - (k - 1);
     up = up >= L ? up - L : up;
+    Clear cl;
     if (o == 0) {
-        clear_region(c, 0, y, 1, back, strip, wv, nwv, wchg);
-        clear_region(c, 1, up, k, x, k, wv, nwv, wchg);
+        cl.a = make_rect(c, 0, y, 1, back, strip);
+        cl.b = make_rect(c, 1, up, k, x, k);
     } else {
-        clear_region(c, 1, up, strip, x, 1, wv, nwv, wchg);
-        clear_region(c, 0, y, k, back, k, wv, nwv, wchg);
+        cl.a = make_rect(c, 1, up, strip, x, 1);
+        cl.b = make_rect(c, 0, y, k, back, k);
+    }
+    return cl;
+}
+
+// One lane's fixed part of a rectangle.  Narrow rectangles (nw <= 64) give
+// every lane one word column: lanes are grouped 2^lg per row, so the lane's
+// word, mask and tile-column offset are the same in every row it visits.
+// Wide rectangles visit one row per round, 64 words at a time.
+struct RectLane {
+    uint32_t rounds;     // wave-uniform number of rounds for this wave
+    uint32_t rsub, rows_per;
+    uint32_t w, colpart;
+    uint64_t mask;
+    uint32_t nchunk;     // wide: 64-word chunks per row
+};
+
+__device__ __forceinline__ RectLane rect_lane(const Ctx &c, const Rect &r, uint32_t wv, uint32_t nwv)
+{
+    const uint32_t lane = lane_id();
+    RectLane rl;
+    if (r.lg != 0xFFFFFFFFu) {
+        rl.rows_per = 64u >> r.lg;
+        rl.rsub = lane >> r.lg;
+        const uint32_t wsub = lane & ((1u << r.lg) - 1);
+        rl.w = wsub < r.nA ? r.a0 + wsub : wsub - r.nA;
+        rl.mask = wsub < r.nw ? col_mask(c.L, r.c0, r.len, rl.w) : 0;
+        rl.colpart = ((rl.w >> c.lg_tw) << 4) + (rl.w & c.tw_m);
+        const uint32_t all = (r.nrows + rl.rows_per - 1) / rl.rows_per;   // row groups
+        rl.rounds = all > wv ? (all - wv + nwv - 1) / nwv : 0;
+        rl.nchunk = 0;
+    } else {
+        rl.nchunk = (r.nw + 63) >> 6;
+        const uint32_t all = r.nrows * rl.nchunk;
+        rl.rounds = all > wv ? (all - wv + nwv - 1) / nwv : 0;
+        rl.rsub = rl.rows_per = rl.w = rl.colpart = 0;
+        rl.mask = 0;
+    }
+    return rl;
+}
+
+// Round rr of wave wv: the word this lane reads (row, bitmap index, mask).
+__device__ __forceinline__ bool rect_round(const Ctx &c, const Rect &r, const RectLane &rl, uint32_t rr,
+                                           uint32_t wv, uint32_t nwv, uint32_t &row, size_t &at,
+                                           uint64_t &mask)
+{
+    const uint32_t g = rr * nwv + wv;   // wave-uniform
+    uint32_t i, w;
+    if (rl.nchunk == 0) {
+        i = g * rl.rows_per + rl.rsub;
+        mask = rl.mask;
+        w = rl.w;
+        if (i >= r.nrows || mask == 0) return false;
+        row = r.row0 + i;
+        row = row >= c.L ? row - c.L : row;
+        at = ((size_t)(row >> c.lg_tr) * c.tpr << 4) + ((row & c.tr_m) << c.lg_tw) + rl.colpart;
+        return true;
+    }
+    i = g / rl.nchunk;
+    const uint32_t j = (g - i * rl.nchunk) * 64 + lane_id();
+    if (j >= r.nw) return false;
+    w = j < r.nA ? r.a0 + j : j - r.nA;
+    mask = col_mask(c.L, r.c0, r.len, w);
+    row = r.row0 + i;
+    row = row >= c.L ? row - c.L : row;
+    at = bm_index(c, row, w);
+    return true;
+}
+
+// Wave wv of nwv clears its share of both rectangles, CAP words in flight
+// per lane: read the words, clear the blocked bits that are still set,
+// decrement the row counts by the bits cleared.
+template <int CAP>
+__device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint32_t wv, uint32_t nwv,
+                                            uint32_t &wchg)
+{
+    const RectLane la = rect_lane(c, cl.a, wv, nwv);
+    const RectLane lb = rect_lane(c, cl.b, wv, nwv);
+    const uint32_t total = la.rounds + lb.rounds;
+    uint64_t *const bma = bitmap(c, cl.a.o);
+    uint64_t *const bmb = bitmap(c, cl.b.o);
+    const uint32_t rba = cl.a.o * c.L, rbb = cl.b.o * c.L;
+    for (uint32_t base = 0; base < total; base += CAP) {
+        uint64_t old[CAP];
+#pragma unroll
+        for (int s = 0; s < CAP; ++s) {
+            const uint32_t rr = base + s;
+            uint32_t row = 0;
+            size_t at = 0;
+            uint64_t mask = 0;
+            bool ok = false;
+            if (rr < la.rounds)
+                ok = rect_round(c, cl.a, la, rr, wv, nwv, row, at, mask);
+            else if (rr < total)
+                ok = rect_round(c, cl.b, lb, rr - la.rounds, wv, nwv, row, at, mask);
+            old[s] = ok ? (rr < la.rounds ? bma : bmb)[at] : 0;
+        }
+#pragma unroll
+        for (int s = 0; s < CAP; ++s) {
+            const uint32_t rr = base + s;
+            uint32_t row = 0;
+            size_t at = 0;
+            uint64_t mask = 0;
+            bool ok = false;
+            const bool in_a = rr < la.rounds;
+            if (in_a)
+                ok = rect_round(c, cl.a, la, rr, wv, nwv, row, at, mask);
+            else if (rr < total)
+                ok = rect_round(c, cl.b, lb, rr - la.rounds, wv, nwv, row, at, mask);
+            const uint64_t hit = ok ? old[s] & mask : 0;
+            if (hit) {
+                (in_a ? bma : bmb)[at] = old[s] & ~hit;
+                count_sub(c, (in_a ? rba : rbb) + row, (uint32_t)__popcll(hit));
+                ++wchg;
+            }
+        }
     }
 }
+
+// Words a lane holds of one bitmap row: lane, lane+64, ... (ROWW of them;
+// ROWW = 1 covers L <= 4096, 8 covers L <= 32768).
+template <int ROWW>
+struct RowWords {
+    uint64_t w[ROWW];
+};
+
+template <int ROWW>
+__device__ __forceinline__ void load_row(const Ctx &c, uint32_t R, RowWords<ROWW> &rw)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t o = R >= c.L ? 1u : 0u, y = R - o * c.L;
+    const uint64_t *bm = bitmap(c, o);
+    const uint32_t per = (c.wd + 63) >> 6;
+#pragma unroll
+    for (uint32_t j = 0; j < ROWW; ++j) {
+        uint32_t wi = lane + 64 * j;
+        rw.w[j] = (j < per && wi < c.wd) ? bm[bm_index(c, y, wi)] : 0;
+    }
+}
+
+// Apply a clear to row words read before it (the clear only ever removes
+// bits inside its masks, so this gives the row as it is after the clear).
+template <int ROWW>
+__device__ __forceinline__ void patch_rect(const Ctx &c, const Rect &r, uint32_t o, uint32_t y,
+                                           RowWords<ROWW> &rw)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t L = c.L;
+    uint32_t dy = y + L - r.row0;
+    dy = dy >= L ? dy - L : dy;
+    if (r.o != o || dy >= r.nrows) return;
+    const uint32_t per = (c.wd + 63) >> 6;
+#pragma unroll
+    for (uint32_t j = 0; j < ROWW; ++j) {
+        uint32_t wi = lane + 64 * j;
+        if (j < per && wi < c.wd) rw.w[j] &= ~col_mask(L, r.c0, r.len, wi);
+    }
+}
+
+template <int ROWW>
+__device__ __forceinline__ void patch_row(const Ctx &c, const Clear &cl, uint32_t R, RowWords<ROWW> &rw)
+{
+    const uint32_t o = R >= c.L ? 1u : 0u, y = R - o * c.L;
+    patch_rect(c, cl.a, o, y, rw);
+    patch_rect(c, cl.b, o, y, rw);
+}
+
+// Hierarchical select on the LDS counts: the row R holding the available
+// placement of rank r (r < A) and r's offset inside that row.  `inc2` and
+// `v2` are this lane's inclusive scan and value over the 4096-row sums.
+__device__ __forceinline__ bool locate_row(const Ctx &c, uint32_t inc2, uint32_t v2, uint32_t r,
+                                           uint32_t &R, uint32_t &rin)
+{
+    const uint32_t lane = lane_id();
+    uint32_t g = 0;
+    if (c.n2 > 1) {
+        uint64_t bal = __ballot(inc2 > r);
+        if (bal == 0) return false;
+        g = first_lane(bal);
+        r -= bcast(inc2 - v2, g);
+    }
+    uint32_t i1 = g * 64 + lane;
+    uint32_t v = i1 < c.n1 ? lds_peek(&c.cnt1[i1]) : 0;
+    uint32_t inc = wave_scan(v);
+    uint64_t bal = __ballot(inc > r);
+    if (bal == 0) return false;
+    uint32_t l1 = first_lane(bal);
+    r -= bcast(inc - v, l1);
+    g = g * 64 + l1;
+    uint32_t i0 = g * 64 + lane;
+    v = i0 < 2 * c.L ? row_count(c, i0) : 0;
+    inc = wave_scan(v);
+    bal = __ballot(inc > r);
+    if (bal == 0) return false;
+    uint32_t l0 = first_lane(bal);
+    r -= bcast(inc - v, l0);
+    R = uniform(g * 64 + l0);
+    rin = uniform(r);
+    return R < 2 * c.L;
+}
+
+// The rin-th available placement of row R: canonical index, or false.
+template <int ROWW>
+__device__ __forceinline__ bool pick_in_row(const Ctx &c, const RowWords<ROWW> &rw, uint32_t R, uint32_t rin,
+                                            uint32_t &P)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t per = (c.wd + 63) >> 6;
+    uint64_t word = 0;
+    uint32_t wsel = 0;
+    bool found = false;
+#pragma unroll
+    for (uint32_t j = 0; j < ROWW; ++j) {
+        if (!found && j < per) {
+            uint32_t pc = (uint32_t)__popcll(rw.w[j]);
+            uint32_t pinc = wave_scan(pc);
+            uint32_t tot = bcast(pinc, 63);
+            if (rin < tot) {
+                uint32_t l = first_lane(__ballot(pinc > rin));
+                rin -= bcast(pinc - pc, l);
+                word = bcast64(rw.w[j], l);
+                wsel = l + 64 * j;
+                found = true;
+            } else {
+                rin -= tot;
+            }
+        }
+    }
+    uint32_t below = (uint32_t)__popcll(word & ((1ull << lane) - 1));
+    uint64_t bal = __ballot(((word >> lane) & 1) && below == rin);
+    if (!found || bal == 0) return false;
+    const uint32_t x = wsel * 64 + first_lane(bal);
+    if (x >= c.L) return false;
+    const uint32_t o = R >= c.L ? 1u : 0u;
+    P = uniform(o * c.L2 + (R - o * c.L) * c.L + x);
+    return true;
+}
+
+// Scan of the 4096-row sums: A_t, and this lane's scan value.
+__device__ __forceinline__ uint32_t scan_top(const Ctx &c, uint32_t &inc2, uint32_t &v2)
+{
+    const uint32_t lane = lane_id();
+    if (c.n2 == 1) {   // one group: its sum is A, no scan needed
+        v2 = lds_peek(&c.cnt2[0]);
+        inc2 = v2;
+        return uniform(v2);
+    }
+    v2 = lane < c.n2 ? lds_peek(&c.cnt2[lane]) : 0;
+    inc2 = wave_scan(v2);
+    return bcast(inc2, 63);
+}
+
+// Rows y0 .. y0+nr-1 of bitmap o read ahead of a clear, flattened: word q =
+// (row - y0) * wd + w is held by lane q % 64 in slot q / 64.
+template <int SPW>
+struct SpecRows {
+    uint64_t w[SPW];
+    uint32_t o, y0, nr;
+};
+
+// Read ahead the rows where the next placement is expected once the clear
+// `cl` has landed.  The next rank lies near u*(A - C)/2^64, and in the counts
+// before the clear up to C further on, where C is the number of placements
+// the clear removes; C is estimated as the rectangles' area times the
+// available fraction A / 2L^2, and the window is centred half-way.
+template <int SPW>
+__device__ __forceinline__ void read_ahead(const Ctx &c, const Clear &cl, uint64_t u, SpecRows<SPW> &sp)
+{
+    const uint32_t lane = lane_id(), L = c.L, wd = c.wd;
+    sp.nr = 0;
+    uint32_t inc2, v2, R, rin;
+    const uint32_t A = scan_top(c, inc2, v2);
+    if (A <= 1) return;
+    const float area = (float)cl.a.nrows * (float)cl.a.len + (float)cl.b.nrows * (float)cl.b.len;
+    uint32_t C = uniform((uint32_t)(area * ((float)A / (2.0f * (float)L * (float)L))));
+    C = C < A ? C : A - 1;
+    const uint32_t r = draw_rank(u, A - C) + C / 2;
+    if (!locate_row(c, inc2, v2, r < A ? r : A - 1, R, rin)) return;
+    const uint32_t o = R >= L ? 1u : 0u, y = R - o * L;
+    const uint32_t nr = c.spec_rows < L ? c.spec_rows : L;
+    uint32_t y0 = y >= nr / 2 ? y - nr / 2 : 0;
+    y0 = y0 + nr > L ? L - nr : y0;
+    sp.o = o;
+    sp.y0 = y0;
+    sp.nr = nr;
+    const uint64_t *bm = bitmap(c, o);
+    const uint32_t nq = nr * wd;
+#pragma unroll
+    for (int j = 0; j < SPW; ++j) {
+        uint32_t q = lane + 64 * j;
+        uint64_t v = 0;
+        if (q < nq) {
+            uint32_t dr = fdiv(q, c.fwd);
+            v = bm[bm_index(c, y0 + dr, q - dr * wd)];
+        }
+        sp.w[j] = v;
+    }
+}
+
+// Row R out of the read-ahead window (the caller checked it is inside).
+template <int SPW, int ROWW>
+__device__ __forceinline__ void row_from_window(const Ctx &c, const SpecRows<SPW> &sp, uint32_t y,
+                                                RowWords<ROWW> &rw)
+{
+    const uint32_t lane = lane_id(), wd = c.wd;
+#pragma unroll
+    for (int j = 0; j < ROWW; ++j) {
+        uint32_t w = lane + 64 * j;
+        uint32_t q = (y - sp.y0) * wd + w;
+        uint32_t src = q & 63, slot = q >> 6;
+        uint64_t val = 0;
+#pragma unroll
+        for (int s = 0; s < SPW; ++s) {
+            uint64_t v = __shfl(sp.w[s], src, 64);
+            if (slot == (uint32_t)s) val = v;
+        }
+        rw.w[j] = w < wd ? val : 0;
+    }
+}
+
+template <int NSEL>
+struct TileCap {
+    static constexpr int value = NSEL == 1 ? 4 : 8;
+};
 
 // ---------------------------------------------------------------------------
 // Selecting wave
 // ---------------------------------------------------------------------------
 
-template <int NSEL>
-__device__ void selector(Ctx &c)
+template <int NSEL, int ROWW>
+__device__ __forceinline__ void selector(Ctx &c)
 {
+    constexpr int CAP = TileCap<NSEL>::value;
+    constexpr int SPW = ROWW == 1 ? 2 : 8;
     const uint32_t lane = lane_id();
-    const uint32_t L = c.L, k = c.k, rows = 2 * L;
+    __builtin_amdgcn_s_setprio(2);   // latency-critical chain first on a shared SIMD
+    const uint32_t L = c.L, k = c.k;
     uint64_t occ = 0, seqh = 0;
     uint32_t wchg = 0;
-    uint64_t u_pre = 0;
+    const bool prof = c.prof != nullptr;
+    uint64_t p_start = prof ? tick() : 0, p_ring = 0, p_sel = 0, p_clr = 0, p0 = 0, spec_hits = 0;
+    uint64_t p_hook = 0, p_proc = 0;
+    uint64_t u_pre = philox_u64(lane, c.sample, c.k0, c.k1);   // draws for steps 0..63 (lane = step)
     uint32_t t = 0;
-    for (;; ++t) {
-        // the labelling wave must have taken ring slot t before it is reused
+    uint32_t P = 0;
+    bool alive = true;
+    {   // first placement
+        uint32_t inc2, v2, R, rin;
+        uint32_t A = scan_top(c, inc2, v2);
+        uint32_t r = uniform(draw_rank(bcast64(u_pre, 0), A));
+        RowWords<ROWW> rw;
+        alive = A > 0 && locate_row(c, inc2, v2, r, R, rin);
+        if (alive) {
+            load_row(c, R, rw);
+            alive = pick_in_row(c, rw, R, rin, P);
+        }
+        if (!alive && A > 0 && lane == 0) c.h->status = kErrSelect;
+    }
+    while (alive) {
+        // ---- step t: P is known.  A correct run never deposits more than
+        // L*L/k k-mers; stop before the k-mer records would overflow.
+        if (t + 1 >= c.ncap) {
+            if (lane == 0) c.h->status = kErrSelect;
+            break;
+        }
         if (t >= kRing) {
+            if (prof) p0 = tick();
             while (!lds_load(&c.h->lab_exit) && t - lds_load(&c.h->lab_progress) >= kRing)
                 __builtin_amdgcn_s_sleep(2);
+            if (prof) p_ring += tick() - p0;
         }
-        // level 2 (4096-row sums) also gives A_t
-        uint32_t v = lane < c.n2 ? lds_peek(&c.cnt2[lane]) : 0;
-        uint32_t inc = wave_scan(v);
-        uint32_t A = __shfl(inc, 63, 64);
-        if (A == 0) break;
-        if ((t & 63) == 0) u_pre = philox_u64(t + lane, c.sample, c.k0, c.k1);
-        uint64_t u = __shfl(u_pre, t & 63, 64);
-        uint32_t r = draw_rank(u, A);
-        uint64_t bal = __ballot(inc > r);
-        if (bal == 0) {   // cannot happen with consistent counts
-            if (lane == 0) c.h->status = kErrSelect;
-            break;
-        }
-        uint32_t g = first_lane(bal);
-        r -= __shfl(inc - v, g, 64);
-        // level 1 (64-row sums)
-        uint32_t i1 = g * 64 + lane;
-        v = i1 < c.n1 ? lds_peek(&c.cnt1[i1]) : 0;
-        inc = wave_scan(v);
-        bal = __ballot(inc > r);
-        if (bal == 0) {
-            if (lane == 0) c.h->status = kErrSelect;
-            break;
-        }
-        uint32_t l1 = first_lane(bal);
-        r -= __shfl(inc - v, l1, 64);
-        g = g * 64 + l1;
-        // level 0 (rows)
-        uint32_t i0 = g * 64 + lane;
-        v = i0 < rows ? row_count(c, i0) : 0;
-        inc = wave_scan(v);
-        bal = __ballot(inc > r);
-        if (bal == 0) {
-            if (lane == 0) c.h->status = kErrSelect;
-            break;
-        }
-        uint32_t l0 = first_lane(bal);
-        r -= __shfl(inc - v, l0, 64);
-        const uint32_t R = g * 64 + l0;
-        const uint32_t o = R >= L ? 1u : 0u;
-        const uint32_t y = R - o * L;
-        // the chosen row: lane holds words lane, lane+64, ...
-        const uint64_t *rowp = c.av[o] + (size_t)y * c.wd;
-        const uint32_t per = (c.wd + 63) >> 6;
-        uint64_t w[8];
-#pragma unroll
-        for (uint32_t j = 0; j < 8; ++j) {
-            uint32_t wi = lane + 64 * j;
-            w[j] = (j < per && wi < c.wd) ? rowp[wi] : 0;
-        }
-        uint64_t word = 0;
-        uint32_t wsel = 0;
-        bool found = false;
-#pragma unroll
-        for (uint32_t j = 0; j < 8; ++j) {
-            if (j < per) {
-                uint32_t pc = (uint32_t)__popcll(w[j]);
-                uint32_t pinc = wave_scan(pc);
-                uint32_t tot = __shfl(pinc, 63, 64);
-                if (r < tot) {
-                    uint32_t l = first_lane(__ballot(pinc > r));
-                    r -= __shfl(pinc - pc, l, 64);
-                    word = __shfl(w[j], l, 64);
-                    wsel = l + 64 * j;
-                    found = true;
-                    break;
-                }
-                r -= tot;
-            }
-        }
-        // r-th set bit of the word
-        uint32_t below = (uint32_t)__popcll(word & ((1ull << lane) - 1));
-        bal = __ballot(((word >> lane) & 1) && below == r);
-        if (!found || bal == 0 || R >= rows) {
-            if (lane == 0) c.h->status = kErrSelect;
-            break;
-        }
-        const uint32_t x = wsel * 64 + first_lane(bal);
-        if (x >= L) {
-            if (lane == 0) c.h->status = kErrSelect;
-            break;
-        }
-        const uint32_t P = o * c.L2 + y * L + x;
-        // hand the placement to the labelling wave
+        if (prof) p0 = tick();
         if (lane == 0) {
             c.ring[t & (kRing - 1)] = P;
             lds_store(&c.h->sel_progress, t + 1);
         }
+        const uint32_t o = P >= c.L2 ? 1u : 0u;
+        const uint32_t rem = P - o * c.L2;
+        const uint32_t y = fdiv(rem, c.fL), x = rem - y * L;
         seqh += mix64(((uint64_t)t << 32) | P);
         for (uint32_t i = lane; i < k; i += 64) {
             uint32_t s;
@@ -444,19 +707,72 @@ __device__ void selector(Ctx &c)
             }
             occ += mix64(((uint64_t)s << 32) | t);
         }
-        if (NSEL > 1) {
-            if (lane == 0) {
-                c.h->cur_p = P;
-                lds_store(&c.h->clr_gen, t + 1);
-            }
+        const Clear cl = make_clear(c, o, y, x);
+        if (NSEL > 1 && lane == 0) {
+            c.h->cur_p = P;
+            lds_store(&c.h->clr_gen, t + 1);
         }
-        clear_blocked(c, o, y, x, 0, NSEL, wchg);
+        // draw for step t+1
+        const uint32_t t1 = t + 1;
+        if ((t1 & 63) == 0) u_pre = philox_u64(t1 + lane, c.sample, c.k0, c.k1);
+        const uint64_t u1 = bcast64(u_pre, t1 & 63);
+        // read the rows where step t+1 will most likely pick, then clear:
+        // the clear's reads are issued after the read-ahead's, so waiting for
+        // them covers both
+        SpecRows<SPW> sp;
+        uint64_t ph = prof ? tick() : 0;
+        read_ahead<SPW>(c, cl, u1, sp);
+        if (prof) {
+            uint64_t ph1 = tick();
+            p_hook += ph1 - ph;
+            ph = ph1;
+        }
+        clear_items<CAP>(c, cl, 0, NSEL, wchg);
+        if (prof) p_proc += tick() - ph;
         if (NSEL > 1) {
             // helpers' bitmap stores must be visible before the next select
-            uint32_t want = (t + 1) * (NSEL - 1);
+            uint32_t want = t1 * (NSEL - 1);
             while (lds_load(&c.h->clr_done) < want) __builtin_amdgcn_s_sleep(1);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
+        if (prof) {
+            uint64_t p1 = tick();
+            p_clr += p1 - p0;
+            p0 = p1;
+        }
+        // ---- exact select for step t+1
+        t = t1;
+        uint32_t inc2, v2, R, rin;
+        const uint32_t A = scan_top(c, inc2, v2);
+        if (A == 0) break;
+        if (!locate_row(c, inc2, v2, draw_rank(u1, A), R, rin)) {
+            if (lane == 0) c.h->status = kErrSelect;
+            break;
+        }
+        RowWords<ROWW> rw;
+        const uint32_t ro = R >= L ? 1u : 0u, ry = R - ro * L;
+        if (sp.nr && ro == sp.o && ry >= sp.y0 && ry < sp.y0 + sp.nr) {
+            row_from_window<SPW, ROWW>(c, sp, ry, rw);
+            patch_row(c, cl, R, rw);
+            ++spec_hits;
+        } else {
+            load_row(c, R, rw);
+        }
+        if (!pick_in_row(c, rw, R, rin, P)) {
+            if (lane == 0) c.h->status = kErrSelect;
+            break;
+        }
+        if (prof) p_sel += tick() - p0;
+    }
+    if (prof) {
+        prof_add(c, kProfSelTotal, tick() - p_start);
+        prof_add(c, kProfSelRing, p_ring);
+        prof_add(c, kProfSelSelect, p_sel);
+        prof_add(c, kProfSelClear, p_clr);
+        prof_add(c, kProfSteps, t);
+        prof_add(c, kProfSpecHits, spec_hits);
+        prof_add(c, kProfSelHook, p_hook);
+        prof_add(c, kProfSelProcess, p_proc);
     }
     occ = wave_sum64(occ);
     uint32_t wsum = wave_sum32(wchg);
@@ -469,9 +785,11 @@ __device__ void selector(Ctx &c)
 }
 
 template <int NSEL>
-__device__ void helper(Ctx &c, uint32_t wv)
+__device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
 {
+    constexpr int CAP = TileCap<NSEL>::value;
     const uint32_t lane = lane_id();
+    __builtin_amdgcn_s_setprio(2);
     uint32_t wchg = 0;
     uint32_t g = 0;
     for (;;) {
@@ -488,12 +806,13 @@ __device__ void helper(Ctx &c, uint32_t wv)
         }
         if (stop) break;
         g = gen;
-        uint32_t P = lds_peek(&c.h->cur_p);
+        uint32_t P = uniform(lds_peek(&c.h->cur_p));
         uint32_t o = P >= c.L2 ? 1u : 0u;
         uint32_t rem = P - o * c.L2;
         uint32_t y = fdiv(rem, c.fL);
         uint32_t x = rem - y * c.L;
-        clear_blocked(c, o, y, x, wv, NSEL, wchg);
+        const Clear cl = make_clear(c, o, y, x);
+        clear_items<CAP>(c, cl, wv, NSEL, wchg);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (lane == 0) atomicAdd(&c.h->clr_done, 1u);
     }
@@ -565,7 +884,7 @@ struct LabelState {
     int32_t nx, ny;
 };
 
-__device__ void reset_slots(const Ctx &c, const LabelState &ls)
+__device__ __forceinline__ void reset_slots(const Ctx &c, const LabelState &ls)
 {
     const uint32_t lane = lane_id();
     for (uint32_t s = lane; s < ls.nb; s += 64) {
@@ -580,7 +899,7 @@ __device__ void reset_slots(const Ctx &c, const LabelState &ls)
 }
 
 // Write the local forest back into the global one.
-__device__ void write_back(const Ctx &c)
+__device__ __forceinline__ void write_back(const Ctx &c)
 {
     const uint32_t lane = lane_id();
     const uint32_t ns = c.h->nslots;
@@ -652,12 +971,15 @@ __device__ __forceinline__ uint32_t resolve_slot(const Ctx &c, const LabelState 
 }
 
 // Resolve the chunk's edges to slots, then merge in deposit order.
-__device__ void process_chunk(const Ctx &c, LabelState &ls, uint32_t ne)
+__device__ __forceinline__ void process_chunk(const Ctx &c, LabelState &ls, uint32_t ne)
 {
     const uint32_t lane = lane_id();
     if (ne == 0) return;
+    const bool prof = c.prof != nullptr;
+    uint64_t p0 = prof ? tick() : 0;
     // every edge can bring two new roots; make room first
     if (c.h->nslots + 2 * ne > kSlots) {
+        prof_add(c, kProfLabFlushes, 1);
         write_back(c);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         uint32_t m_first = c.e_step[0];
@@ -682,6 +1004,11 @@ __device__ void process_chunk(const Ctx &c, LabelState &ls, uint32_t ne)
         }
     }
     __builtin_amdgcn_wave_barrier();
+    if (prof) {
+        uint64_t p1 = tick();
+        prof_add(c, kProfLabResolve, p1 - p0);
+        p0 = p1;
+    }
     // merge in deposit order (every lane walks the same list)
     int32_t nx = ls.nx, ny = ls.ny;
     for (uint32_t e = 0; e < ne; ++e) {
@@ -717,9 +1044,57 @@ __device__ void process_chunk(const Ctx &c, LabelState &ls, uint32_t ne)
     ls.nx = nx;
     ls.ny = ny;
     __builtin_amdgcn_wave_barrier();
+    if (prof) prof_add(c, kProfLabMerge, tick() - p0);
 }
 
-__device__ void labeler(Ctx &c, bool track)
+// Contact q of a batch starting at deposit tl: deposit m = tl + q / (2k+2),
+// index ci of the contact along it, the site ii of m it touches, the unit
+// step e and the neighbouring site b = anchor_m + ii * u_m + e (mod L).
+struct Contact {
+    bool act;
+    uint32_t m, ci, bx, by;
+    int32_t ii, ex, ey, umx, umy;
+};
+
+__device__ __forceinline__ Contact contact_of(const Ctx &c, uint32_t tl, uint32_t q, uint32_t total)
+{
+    const uint32_t L = c.L, k = c.k;
+    Contact ct;
+    ct.act = q < total;
+    const uint32_t i = ct.act ? fdiv(q, c.fC) : 0;
+    ct.ci = q - i * (2 * k + 2);
+    ct.m = tl + i;
+    const uint32_t am = c.banc[i];
+    const uint32_t om = am >> 31, site = am & 0x7FFFFFFFu;
+    const uint32_t ay = fdiv(site, c.fL), ax = site - ay * L;
+    ct.umx = om ? 0 : 1;
+    ct.umy = om ? 1 : 0;
+    if (ct.ci < k) {
+        ct.ii = (int32_t)ct.ci;
+        ct.ex = om ? -1 : 0;
+        ct.ey = om ? 0 : -1;
+    } else if (ct.ci < 2 * k) {
+        ct.ii = (int32_t)(ct.ci - k);
+        ct.ex = om ? 1 : 0;
+        ct.ey = om ? 0 : 1;
+    } else if (ct.ci == 2 * k) {
+        ct.ii = 0;
+        ct.ex = -ct.umx;
+        ct.ey = -ct.umy;
+    } else {
+        ct.ii = (int32_t)k - 1;
+        ct.ex = ct.umx;
+        ct.ey = ct.umy;
+    }
+    int32_t bx = (int32_t)ax + ct.ii * ct.umx + ct.ex, by = (int32_t)ay + ct.ii * ct.umy + ct.ey;
+    bx = bx >= (int32_t)L ? bx - (int32_t)L : (bx < 0 ? bx + (int32_t)L : bx);
+    by = by >= (int32_t)L ? by - (int32_t)L : (by < 0 ? by + (int32_t)L : by);
+    ct.bx = (uint32_t)bx;
+    ct.by = (uint32_t)by;
+    return ct;
+}
+
+__device__ __forceinline__ void labeler(Ctx &c, bool track)
 {
     const uint32_t lane = lane_id();
     const uint32_t L = c.L, k = c.k, nC = 2 * k + 2;
@@ -728,9 +1103,13 @@ __device__ void labeler(Ctx &c, bool track)
     ls.nx = -1;
     ls.ny = -1;
     uint32_t tl = 0;
+    const bool prof = c.prof != nullptr;
+    uint64_t p_start = prof ? tick() : 0, p0 = 0;
+    uint64_t p_idle = 0, p_map = 0, p_gather = 0, p_batches = 0, p_edges = 0;
     for (;;) {
         uint32_t sp;
         bool finished = false;
+        if (prof) p0 = tick();
         for (;;) {
             sp = lds_load(&c.h->sel_progress);
             if (sp > tl) break;
@@ -740,6 +1119,12 @@ __device__ void labeler(Ctx &c, bool track)
                 break;
             }
             __builtin_amdgcn_s_sleep(2);
+        }
+        if (prof) {
+            uint64_t p1 = tick();
+            p_idle += p1 - p0;
+            p0 = p1;
+            ++p_batches;
         }
         if (finished) break;
         const uint32_t B = sp - tl < kBatch ? sp - tl : kBatch;
@@ -762,108 +1147,118 @@ __device__ void labeler(Ctx &c, bool track)
             uint32_t site = a & 0x7FFFFFFFu;
             uint32_t ay = fdiv(site, c.fL), ax = site - ay * L;
             if (a >> 31) {
-                uint32_t yy = ay + s;
-                yy = yy >= L ? yy - L : yy;
-                site = yy * L + ax;
+                ay += s;
+                ay = ay >= L ? ay - L : ay;
             } else {
-                uint32_t xx = ax + s;
-                xx = xx >= L ? xx - L : xx;
-                site = ay * L + xx;
+                ax += s;
+                ax = ax >= L ? ax - L : ax;
             }
-            c.map[site] = (int32_t)(tl + i);
+            c.map[map_index(c, ay, ax)] = (int32_t)(tl + i);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        if (prof) {
+            uint64_t p1 = tick();
+            p_map += p1 - p0;
+            p0 = p1;
+        }
         ls.base = tl;
         ls.nb = B;
         reset_slots(c, ls);
         __builtin_amdgcn_wave_barrier();
         // contacts of every deposit of the batch, in deposit order:
         // c in [0,k): above (H) / left (V) of site c; [k,2k): below / right;
-        // 2k: before site 0; 2k+1: after site k-1
+        // 2k: before site 0; 2k+1: after site k-1.  kGather rounds of 64
+        // contacts have their map reads in flight together, then their
+        // k-mer record reads, then are compacted in order.
         uint32_t ne = 0;
         int32_t cn = -1, cvx = 0, cvy = 0;
         const uint32_t total = B * nC;
         bool stop = false;
-        for (uint32_t q0 = 0; q0 < total && !stop; q0 += 64) {
-            uint32_t q = q0 + lane;
-            bool act = q < total;
-            uint32_t i = act ? fdiv(q, fC) : 0;
-            uint32_t ci = q - i * nC;
-            uint32_t m = tl + i;
-            uint32_t am = c.banc[i];
-            uint32_t om = am >> 31, site = am & 0x7FFFFFFFu;
-            uint32_t ay = fdiv(site, c.fL), ax = site - ay * L;
-            int32_t umx = om ? 0 : 1, umy = om ? 1 : 0;
-            int32_t ii, ex, ey;
-            if (ci < k) {
-                ii = (int32_t)ci;
-                ex = om ? -1 : 0;
-                ey = om ? 0 : -1;
-            } else if (ci < 2 * k) {
-                ii = (int32_t)(ci - k);
-                ex = om ? 1 : 0;
-                ey = om ? 0 : 1;
-            } else if (ci == 2 * k) {
-                ii = 0;
-                ex = -umx;
-                ey = -umy;
-            } else {
-                ii = (int32_t)k - 1;
-                ex = umx;
-                ey = umy;
+        for (uint32_t g0 = 0; g0 < total && !stop; g0 += 64 * kGather) {
+            int32_t nval[kGather];
+            uint32_t aval[kGather];
+#pragma unroll
+            for (int g = 0; g < kGather; ++g) {
+                Contact ct = contact_of(c, tl, g0 + 64 * g + lane, total);
+                nval[g] = ct.act ? c.map[map_index(c, ct.by, ct.bx)] : -1;
             }
-            // neighbour b = anchor + ii*u_m + e (mod L)
-            int32_t bx = (int32_t)ax + ii * umx + ex, by = (int32_t)ay + ii * umy + ey;
-            bx = bx >= (int32_t)L ? bx - (int32_t)L : (bx < 0 ? bx + (int32_t)L : bx);
-            by = by >= (int32_t)L ? by - (int32_t)L : (by < 0 ? by + (int32_t)L : by);
-            int32_t n = act ? c.map[(uint32_t)by * L + (uint32_t)bx] : -1;
-            bool keep = act && n >= 0 && (uint32_t)n <= m;
-            int32_t vx = 0, vy = 0;
-            if (keep) {
-                uint32_t an = (uint32_t)n >= tl ? c.banc[(uint32_t)n - tl] : c.kmer[n];
-                uint32_t on = an >> 31, ns = an & 0x7FFFFFFFu;
-                uint32_t ny_ = fdiv(ns, c.fL), nx_ = ns - ny_ * L;
-                int32_t j = on ? by - (int32_t)ny_ : bx - (int32_t)nx_;
-                j = j < 0 ? j + (int32_t)L : j;
-                int32_t unx = on ? 0 : 1, uny = on ? 1 : 0;
-                // v = anchor_m - anchor_n through this contact, unwrapped
-                vx = j * unx - ii * umx - ex;
-                vy = j * uny - ii * umy - ey;
+#pragma unroll
+            for (int g = 0; g < kGather; ++g) {
+                uint32_t m = tl + fdiv(g0 + 64 * g + lane, fC);
+                int32_t n = nval[g];
+                bool keep = n >= 0 && (uint32_t)n <= m;
+                aval[g] = 0;
+                if (keep) aval[g] = (uint32_t)n >= tl ? c.banc[(uint32_t)n - tl] : c.kmer[n];
             }
-            // drop a contact equal to the previous one on the same side
-            int32_t key = keep ? n : -1;
-            int32_t pn = __shfl_up(key, 1, 64), pvx = __shfl_up(vx, 1, 64), pvy = __shfl_up(vy, 1, 64);
-            if (lane == 0) {
-                pn = cn;
-                pvx = cvx;
-                pvy = cvy;
-            }
-            bool same_run = ci > 0 && ci < 2 * k && ci != k;
-            bool emit = keep && !(same_run && pn == n && pvx == vx && pvy == vy);
-            cn = __shfl(key, 63, 64);
-            cvx = __shfl(vx, 63, 64);
-            cvy = __shfl(vy, 63, 64);
-            uint64_t bal = __ballot(emit);
-            uint32_t off = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
-            if (emit) {
-                uint32_t idx = ne + off;
-                c.e_step[idx] = m;
-                c.e_ms[idx] = (uint32_t)n;
-                c.e_vx[idx] = vx;
-                c.e_vy[idx] = vy;
-            }
-            ne += (uint32_t)__popcll(bal);
-            __builtin_amdgcn_wave_barrier();
-            if (ne + 64 > kEdges || q0 + 64 >= total) {
-                process_chunk(c, ls, ne);
-                ne = 0;
-                if (!track && ls.nx >= 0 && ls.ny >= 0) stop = true;
-                if (c.h->status != 0) stop = true;
+#pragma unroll
+            for (int g = 0; g < kGather; ++g) {
+                const uint32_t q0 = g0 + 64 * g;
+                if (q0 >= total || stop) continue;
+                Contact ct = contact_of(c, tl, q0 + lane, total);
+                int32_t n = nval[g];
+                bool keep = ct.act && n >= 0 && (uint32_t)n <= ct.m;
+                int32_t vx = 0, vy = 0;
+                if (keep) {
+                    uint32_t an = aval[g];
+                    uint32_t on = an >> 31, ns = an & 0x7FFFFFFFu;
+                    uint32_t ny_ = fdiv(ns, c.fL), nx_ = ns - ny_ * L;
+                    int32_t j = on ? (int32_t)ct.by - (int32_t)ny_ : (int32_t)ct.bx - (int32_t)nx_;
+                    j = j < 0 ? j + (int32_t)L : j;
+                    int32_t unx = on ? 0 : 1, uny = on ? 1 : 0;
+                    // v = anchor_m - anchor_n through this contact, unwrapped
+                    vx = j * unx - ct.ii * ct.umx - ct.ex;
+                    vy = j * uny - ct.ii * ct.umy - ct.ey;
+                }
+                // drop a contact equal to the previous one on the same side
+                int32_t key = keep ? n : -1;
+                int32_t pn = __shfl_up(key, 1, 64), pvx = __shfl_up(vx, 1, 64), pvy = __shfl_up(vy, 1, 64);
+                if (lane == 0) {
+                    pn = cn;
+                    pvx = cvx;
+                    pvy = cvy;
+                }
+                bool same_run = ct.ci > 0 && ct.ci < 2 * k && ct.ci != k;
+                bool emit = keep && !(same_run && pn == n && pvx == vx && pvy == vy);
+                cn = (int32_t)bcast((uint32_t)key, 63);
+                cvx = (int32_t)bcast((uint32_t)vx, 63);
+                cvy = (int32_t)bcast((uint32_t)vy, 63);
+                uint64_t bal = __ballot(emit);
+                uint32_t off = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
+                if (emit) {
+                    uint32_t idx = ne + off;
+                    c.e_step[idx] = ct.m;
+                    c.e_ms[idx] = (uint32_t)n;
+                    c.e_vx[idx] = vx;
+                    c.e_vy[idx] = vy;
+                }
+                ne += (uint32_t)__popcll(bal);
+                __builtin_amdgcn_wave_barrier();
+                if (ne + 64 > kEdges || q0 + 64 >= total) {
+                    if (prof) {
+                        p_gather += tick() - p0;
+                        p_edges += ne;
+                    }
+                    process_chunk(c, ls, ne);
+                    if (prof) p0 = tick();
+                    ne = 0;
+                    if (!track && ls.nx >= 0 && ls.ny >= 0) stop = true;
+                    if (c.h->status != 0) stop = true;
+                }
             }
         }
         if (stop) break;
+        if (prof) p0 = tick();
         write_back(c);
+        if (prof) prof_add(c, kProfLabWriteBack, tick() - p0);
         tl = t1;
+    }
+    if (prof) {
+        prof_add(c, kProfLabTotal, tick() - p_start);
+        prof_add(c, kProfLabIdle, p_idle);
+        prof_add(c, kProfLabMap, p_map);
+        prof_add(c, kProfLabGather, p_gather);
+        prof_add(c, kProfLabBatches, p_batches);
+        prof_add(c, kProfLabEdges, p_edges);
     }
     if (lane == 0) {
         c.h->nx = ls.nx;
@@ -876,7 +1271,7 @@ __device__ void labeler(Ctx &c, bool track)
 // One sample, then the persistent loop
 // ---------------------------------------------------------------------------
 
-__device__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, uint8_t *lds)
+__device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, uint8_t *lds)
 {
     c.L = d.L;
     c.k = d.k;
@@ -890,9 +1285,24 @@ __device__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, uint8_t *lds)
     c.fL = d.fL;
     c.fk = d.fk;
     c.fC = d.fC;
+    c.fwd = d.fwd;
+    c.fwp = d.fwp;
+    c.wp = padded_words(d.L);
+    c.lp = padded_side(d.L);
+    c.lg_tr = d.lg_tr;
+    c.lg_tw = 4 - d.lg_tr;
+    c.tr_m = (1u << c.lg_tr) - 1;
+    c.tw_m = (1u << c.lg_tw) - 1;
+    c.tpr = c.wp >> c.lg_tw;
+    c.lg_mr = d.lg_mr;
+    c.lg_mc = 5 - d.lg_mr;
+    c.mr_m = (1u << c.lg_mr) - 1;
+    c.mc_m = (1u << c.lg_mc) - 1;
+    c.mtpr = c.lp >> c.lg_mc;
+    c.spec_rows = d.spec_rows;
     SlabLayout s = slab_layout(d.L, d.k);
-    c.av[0] = (uint64_t *)(slab + s.avail0);
-    c.av[1] = (uint64_t *)(slab + s.avail1);
+    c.av0 = (uint64_t *)(slab + s.avail0);
+    c.av1 = (uint64_t *)(slab + s.avail1);
     c.map = (int32_t *)(slab + s.map);
     c.node = (int4 *)(slab + s.node);
     c.kmer = (uint32_t *)(slab + s.kmer);
@@ -918,34 +1328,37 @@ __device__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, uint8_t *lds)
     c.h_val = c.h_key + kHash;
 }
 
-template <int NSEL>
-__device__ void run_sample(const KernelArgs &a, const DevDesc &d, uint8_t *lds)
+template <int NSEL, int ROWW>
+__device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d, uint8_t *lds)
 {
     constexpr uint32_t NT = 64 * (NSEL + 1);
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid >> 6;
     Ctx c;
     carve(c, d, a.slabs + (size_t)blockIdx.x * a.slab_stride, lds);
+    c.prof = a.prof ? a.prof + (size_t)d.out * kProfSlots : nullptr;
+    const uint64_t p_init = c.prof ? tick() : 0;
     const uint32_t L = c.L;
     const bool h_only = (c.flags & 1u) != 0;
     const bool track = (c.flags & 2u) != 0;
 
     // ---- initial state (Sec. II.A): all sites empty, all placements free
     {
-        const size_t n2 = (size_t)c.L2;
+        // the padded map (a multiple of 32 x 32 sites) is all -1
         int4 *m4 = (int4 *)c.map;
-        const size_t q4 = n2 / 4;
+        const size_t q4 = (size_t)c.lp * c.lp / 4;
         for (size_t i = tid; i < q4; i += NT) m4[i] = make_int4(-1, -1, -1, -1);
-        for (size_t i = q4 * 4 + tid; i < n2; i += NT) c.map[i] = -1;
+        // bitmaps: every anchor of a real row and column available, padding 0
         const uint32_t wd = c.wd;
         const uint32_t tailbits = L & 63u;
         const uint64_t last = tailbits ? ((1ull << tailbits) - 1) : ~0ull;
-        const size_t nwords = (size_t)L * wd;
-        for (size_t i = tid; i < nwords; i += NT) {
-            uint32_t wi = (uint32_t)(i % wd);
-            uint64_t full = wi == wd - 1 ? last : ~0ull;
-            c.av[0][i] = full;
-            c.av[1][i] = h_only ? 0ull : full;
+        const uint32_t nwords = c.lp * c.wp;
+        for (uint32_t i = tid; i < nwords; i += NT) {
+            uint32_t row = fdiv(i, c.fwp), wi = i - row * c.wp;
+            uint64_t full = (row >= L || wi >= wd) ? 0ull : (wi == wd - 1 ? last : ~0ull);
+            size_t at = bm_index(c, row, wi);
+            c.av0[at] = full;
+            c.av1[at] = h_only ? 0ull : full;
         }
         const uint32_t rows = 2 * L;
         const uint32_t vcount = h_only ? 0u : L;
@@ -986,10 +1399,11 @@ __device__ void run_sample(const KernelArgs &a, const DevDesc &d, uint8_t *lds)
         }
     }
     __syncthreads();
+    if (c.prof && tid == 0) atomicAdd(&c.prof[kProfInit], (unsigned long long)(tick() - p_init));
 
     // ---- the two chains
     if (wave == 0)
-        selector<NSEL>(c);
+        selector<NSEL, ROWW>(c);
     else if (wave < (uint32_t)NSEL)
         helper<NSEL>(c, wave);
     else
@@ -1026,7 +1440,7 @@ __device__ void run_sample(const KernelArgs &a, const DevDesc &d, uint8_t *lds)
         r.n_clusters_jam = track ? (int32_t)c.h->nclusters : -1;
         r.n_nonwrapping_jam = track ? (int32_t)c.h->nonwrap : -1;
         r.status = c.h->status;
-        r.tile = (int32_t)a.tile;
+        r.tile = (int32_t)d.tile;
         r.wchg_words = c.h->wchg;
         r.alg_bytes = 4 * Lw * Lw + 16 * Lw * c.wd +
                       (uint64_t)njam * (4 * kw + 4 * (2 * kw + 2) + 8 * c.wd + 16) + 16 * r.wchg_words;
@@ -1035,7 +1449,7 @@ __device__ void run_sample(const KernelArgs &a, const DevDesc &d, uint8_t *lds)
     __syncthreads();
 }
 
-template <int NSEL>
+template <int NSEL, int ROWW>
 __global__ __launch_bounds__(64 * (NSEL + 1)) void rsa_persistent(KernelArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -1047,7 +1461,7 @@ __global__ __launch_bounds__(64 * (NSEL + 1)) void rsa_persistent(KernelArgs a)
         __syncthreads();
         if (i >= a.n) return;
         const DevDesc d = a.descs[i];
-        run_sample<NSEL>(a, d, lds);
+        run_sample<NSEL, ROWW>(a, d, lds);
     }
 }
 
@@ -1059,13 +1473,14 @@ __global__ void rsa_reset_queues(uint32_t *queues, uint32_t n)
 
 }  // namespace rsa
 
-// Host-visible launch table.
+// Host-visible launch table: [tile][row words per lane 1 or 8].
 namespace rsa {
-using KernelFn = void (*)(KernelArgs);
-extern const void *kPersistentKernels[kNumTiles];
-const void *kPersistentKernels[kNumTiles] = {
-    (const void *)&rsa_persistent<kTileWaves[0]>, (const void *)&rsa_persistent<kTileWaves[1]>,
-    (const void *)&rsa_persistent<kTileWaves[2]>, (const void *)&rsa_persistent<kTileWaves[3]>,
-    (const void *)&rsa_persistent<kTileWaves[4]>};
+extern const void *kPersistentKernels[kNumWaveTiles][2];
+const void *kPersistentKernels[kNumWaveTiles][2] = {
+    {(const void *)&rsa_persistent<kTileWaves[0], 1>, (const void *)&rsa_persistent<kTileWaves[0], 8>},
+    {(const void *)&rsa_persistent<kTileWaves[1], 1>, (const void *)&rsa_persistent<kTileWaves[1], 8>},
+    {(const void *)&rsa_persistent<kTileWaves[2], 1>, (const void *)&rsa_persistent<kTileWaves[2], 8>},
+    {(const void *)&rsa_persistent<kTileWaves[3], 1>, (const void *)&rsa_persistent<kTileWaves[3], 8>},
+    {(const void *)&rsa_persistent<kTileWaves[4], 1>, (const void *)&rsa_persistent<kTileWaves[4], 8>}};
 const void *kResetKernel = (const void *)&rsa_reset_queues;
 }  // namespace rsa

@@ -20,13 +20,18 @@ RSA_OK, RSA_EINVAL, RSA_ENOMEM, RSA_EDEVICE, RSA_ENOTREADY, RSA_EBUSY, RSA_ENOTF
     0, -1, -2, -3, -4, -5, -6)
 FLAG_H_ONLY = 1
 FLAG_TRACK_CLUSTERS = 2
-OPT_MODE, OPT_TILE, OPT_GRAPH, OPT_SLOTS = 1, 2, 3, 4
+OPT_MODE, OPT_TILE, OPT_GRAPH, OPT_SLOTS, OPT_PROFILE = 1, 2, 3, 4, 5
+PROFILE_SLOTS = ("init", "sel_total", "sel_ring", "sel_select", "sel_clear", "lab_total", "lab_idle",
+                 "lab_map", "lab_gather", "lab_resolve", "lab_merge", "lab_writeback",
+                 "lab_batches", "lab_edges", "lab_flushes", "steps", "spec_hits", "sel_hook",
+                 "sel_process")
 MODE_BATCHED, MODE_PLAIN = 0, 1
 
 # Symbols declared in include/rsa.h.
 EXPORTS = ("rsa_create", "rsa_footprint_bytes", "rsa_run_batch", "rsa_results",
-           "rsa_batch_elapsed_ms", "rsa_destroy", "rsa_strerror", "rsa_last_error",
-           "rsa_set_option", "rsa_get_option", "rsa_num_tiles", "rsa_tile_for_shape")
+           "rsa_batch_elapsed_ms", "rsa_batch_profile", "rsa_destroy", "rsa_strerror", "rsa_last_error",
+           "rsa_set_option", "rsa_get_option", "rsa_num_tiles", "rsa_tile_for_shape",
+           "rsa_tile_shape")
 
 
 class Sample(ctypes.Structure):
@@ -82,6 +87,9 @@ def lib() -> ctypes.CDLL:
     L.rsa_results.restype = i32
     L.rsa_batch_elapsed_ms.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_float)]
     L.rsa_batch_elapsed_ms.restype = i32
+    L.rsa_batch_profile.argtypes = [vp, u64, ctypes.POINTER(u64), u32, ctypes.POINTER(u32),
+                                    ctypes.POINTER(u32)]
+    L.rsa_batch_profile.restype = i32
     L.rsa_destroy.argtypes = [vp]
     L.rsa_destroy.restype = None
     L.rsa_strerror.argtypes = [i32]
@@ -96,6 +104,9 @@ def lib() -> ctypes.CDLL:
     L.rsa_num_tiles.restype = i32
     L.rsa_tile_for_shape.argtypes = [u32, u32]
     L.rsa_tile_for_shape.restype = i32
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.rsa_tile_shape.argtypes = [i32, ip, ip, ip]
+    L.rsa_tile_shape.restype = i32
     _lib = L
     return L
 
@@ -114,6 +125,15 @@ def num_tiles() -> int:
 
 def tile_for_shape(L: int, k: int) -> int:
     return lib().rsa_tile_for_shape(L, k)
+
+
+def tile_shape(tile: int) -> tuple[int, int, int]:
+    """(waves sharing select/clear, bitmap tile rows, map tile rows)."""
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    rc = lib().rsa_tile_shape(tile, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    if rc != RSA_OK:
+        raise RsaError(rc, "rsa_tile_shape")
+    return a.value, b.value, c.value
 
 
 def make_samples(descs: Iterable[Sequence[int]]):
@@ -206,6 +226,19 @@ class Context:
         if rc != RSA_OK:
             raise RsaError(rc, self.last_error())
         return float(ms.value)
+
+    def profile(self, batch):
+        """Per-sample phase counters of a batch run with OPT_PROFILE = 1:
+        (list of dicts, tick rate in kHz)."""
+        bid, n = batch
+        slots, khz = ctypes.c_uint32(), ctypes.c_uint32()
+        out = (ctypes.c_uint64 * (max(n, 1) * len(PROFILE_SLOTS)))()
+        rc = self._lib.rsa_batch_profile(self._h, bid, out, n, ctypes.byref(slots), ctypes.byref(khz))
+        if rc != RSA_OK:
+            raise RsaError(rc, self.last_error())
+        m = slots.value
+        assert m == len(PROFILE_SLOTS)
+        return [dict(zip(PROFILE_SLOTS, out[i * m:(i + 1) * m])) for i in range(n)], khz.value
 
     def results(self, batch, wait: bool = True):
         """Results of a batch as a list of dicts (None if not ready and

@@ -38,11 +38,13 @@ def test_every_declared_symbol_is_exported(rsa):
 def test_footprint_matches_layout(rsa):
     # two bitmaps of L*ceil(L/64) words, int32 map, 20 B per k-mer record,
     # every area 256-byte aligned
+    # (rows and columns padded so that every 128-byte tile shape fits)
     def expect(L, k):
         a = lambda v: (v + 255) // 256 * 256
-        wd = (L + 63) // 64
+        wp = ((L + 63) // 64 + 15) // 16 * 16
+        lp = (L + 31) // 32 * 32
         cap = L * L // k + 1
-        return a(L * wd * 8) * 2 + a(4 * L * L) + a(16 * cap) + a(4 * cap)
+        return a(lp * wp * 8) * 2 + a(4 * lp * lp) + a(16 * cap) + a(4 * cap)
 
     for L, k in [(1, 1), (5, 3), (64, 8), (1024, 64), (16384, 1024), (32768, 4096)]:
         assert rsa.footprint_bytes(L, k) == expect(L, k)
@@ -61,6 +63,13 @@ def test_strerror_and_tiles(rsa):
     for L, k in [(64, 8), (1024, 64), (4096, 256), (16384, 1024), (32768, 4096)]:
         assert 0 <= rsa.tile_for_shape(L, k) < n
     assert rsa.tile_for_shape(4, 5) == rsa.RSA_EINVAL
+    shapes = {rsa.tile_shape(t) for t in range(n)}
+    assert len(shapes) == n
+    for waves, tr, mr in shapes:
+        assert 1 <= waves <= 15 and tr in (1, 2, 4, 8, 16) and mr in (1, 2, 4, 8, 16, 32)
+        assert 64 * (waves + 1) <= 1024
+    with pytest.raises(rsa.RsaError):
+        rsa.tile_shape(n)
 
 
 def test_workloads_shapes():

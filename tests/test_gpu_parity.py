@@ -113,7 +113,9 @@ def test_tiles_and_modes_agree(ctx, orc):
     try:
         for tile in range(rsa.num_tiles()):
             ctx.set_option(rsa.OPT_TILE, tile)
-            check(descs, ctx.run(descs), want, census=True)
+            got = ctx.run(descs)
+            check(descs, got, want, census=True)
+            assert all(g["tile"] == tile for g in got)
         ctx.set_option(rsa.OPT_TILE, -1)
         ctx.set_option(rsa.OPT_MODE, rsa.MODE_PLAIN)
         check(descs, ctx.run(descs), want, census=True)
@@ -147,6 +149,30 @@ def test_graph_replays_repeat(ctx, orc):
         x = torch.ones(1 << 20, device="cuda")
         torch.cuda.synchronize()
         assert float(x.sum()) == float(1 << 20)
+
+
+def test_wide_rows(ctx, orc):
+    """Rows of more than 64 bitmap words (L > 4096) use the wide kernels."""
+    descs = [(4160, 64, 7, s, 0) for s in range(3)] + [(4097, 300, 1, 0, 2)]
+    _log("wide rows: (4160, 64) x 3, (4097, 300)")
+    got = ctx.run(descs)
+    check(descs, got, orc.run_many(descs), census=True)
+
+
+def test_mixed_batch_workload(ctx, orc):
+    """The uneven batch: 512 samples over five (L, k) shapes in one graph;
+    the oracle checks the first ten samples of every shape."""
+    from paper_1810_06800_amd import workloads
+
+    descs = workloads.mixed_batch()
+    _log("mixed batch: 512 samples")
+    got = ctx.run(descs)
+    assert all(g["status"] == 0 for g in got)
+    pick = []
+    for shape in workloads.MIXED_SHAPES:
+        pick += [i for i, d in enumerate(descs) if d[:2] == shape][:10]
+    sub = [descs[i] for i in pick]
+    check(sub, [got[i] for i in pick], orc.run_many(sub, threads=min(16, os.cpu_count() or 1)))
 
 
 def test_invalid_descriptors_rejected(ctx):
