@@ -202,14 +202,17 @@ int rsa_get_option(rsa_ctx *ctx, int option, int64_t *value);
 
 /* Schedules ("tiles").  A tile fixes the waves that share one sample's
  * select/clear (one more wave labels clusters), the height of the 128-byte
- * bitmap tiles (1..16 rows of 16..1 words) and of the 128-byte site-map tiles
- * (1..32 rows of 32..1 sites).  Results never depend on the tile.
- * rsa_num_tiles: how many exist; rsa_tile_for_shape: the one the autotune
- * table picks for (L, k) (RSA_EINVAL for an invalid shape); rsa_tile_shape:
- * decode a tile id (RSA_EINVAL if out of range; NULL outputs are skipped). */
+ * bitmap tiles (1..16 rows of 16..1 words), the height of the 128-byte
+ * site-map tiles (1..32 rows of 32..1 sites), and the clear mode (0 dense:
+ * every word of the blocked rectangles is read; 1 sparse: per-word summary
+ * bits are read first and only words that are still non-zero are touched).
+ * Results never depend on the tile.  rsa_num_tiles: how many exist;
+ * rsa_tile_for_shape: the one the autotune table picks for (L, k)
+ * (RSA_EINVAL for an invalid shape); rsa_tile_shape: decode a tile id
+ * (RSA_EINVAL if out of range; NULL outputs are skipped). */
 int rsa_num_tiles(void);
 int rsa_tile_for_shape(uint32_t L, uint32_t k);
-int rsa_tile_shape(int tile, int *waves, int *bitmap_tile_rows, int *map_tile_rows);
+int rsa_tile_shape(int tile, int *waves, int *bitmap_tile_rows, int *map_tile_rows, int *sparse);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@
 #include "rsa_device.h"
 
 namespace rsa {
-extern const void *kPersistentKernels[kNumWaveTiles][2];
+extern const void *kPersistentKernels[kNumWaveTiles][2][2];
 extern const void *kResetKernel;
 }  // namespace rsa
 
@@ -37,6 +37,7 @@ constexpr int kPlainStreams = 4;
 struct Group {
     int waves;               // index into kTileWaves (the kernel instantiation)
     int wide;                // rows of more than 64 words (L > 4096)
+    int sparse;              // clear mode
     uint32_t first, count;   // range in the planned descriptor array
     uint32_t grid;
     uint32_t lds;
@@ -124,8 +125,8 @@ bool valid_sample(const rsa_sample_t &s)
 int default_tile(uint32_t L, uint32_t k)
 {
     (void)L;
-    int waves = k <= 64 ? 0 : (k <= 128 ? 1 : (k <= 256 ? 2 : (k <= 1024 ? 3 : 4)));
-    return make_tile(waves, 3, 3);
+    int waves = k <= 64 ? 0 : (k <= 128 ? 1 : (k <= 256 ? 2 : 3));
+    return make_tile(waves, 3, 3, k >= 512 ? 1 : 0);
 }
 
 // Relative cost of a sample: deposits (about 0.7 L^2 / k) times the words a
@@ -198,11 +199,12 @@ void give_block(rsa_ctx *c, Block b)
     if (b.ptr) c->pool.push_back(b);
 }
 
-int resident_blocks(rsa_ctx *c, int tile, int wide, uint32_t lds)
+int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, uint32_t lds)
 {
     int nb = 0;
     int threads = 64 * (kTileWaves[tile] + 1);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kPersistentKernels[tile][wide], threads, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kPersistentKernels[tile][wide][sparse], threads,
+                                                     lds) !=
             hipSuccess ||
         nb < 1)
         nb = 1;
@@ -226,6 +228,7 @@ DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile)
     d.fwd = make_fastdiv(d.wd);
     d.fwp = make_fastdiv(padded_words(s.L));
     d.tile = (uint32_t)tile;
+    d.sparse = (uint32_t)tile_sparse(tile);
     d.lg_tr = (uint32_t)tile_lg_tr(tile);
     d.lg_mr = (uint32_t)tile_lg_mr(tile);
     // read-ahead window: as many rows as two (eight for wide rows) words per
@@ -294,12 +297,13 @@ int rsa_tile_for_shape(uint32_t L, uint32_t k)
     return default_tile(L, k);
 }
 
-int rsa_tile_shape(int tile, int *waves, int *bitmap_tile_rows, int *map_tile_rows)
+int rsa_tile_shape(int tile, int *waves, int *bitmap_tile_rows, int *map_tile_rows, int *sparse)
 {
     if (tile < 0 || tile >= kNumTiles) return RSA_EINVAL;
     if (waves) *waves = kTileWaves[tile_waves(tile)];
     if (bitmap_tile_rows) *bitmap_tile_rows = 1 << tile_lg_tr(tile);
     if (map_tile_rows) *map_tile_rows = 1 << tile_lg_mr(tile);
+    if (sparse) *sparse = tile_sparse(tile);
     return RSA_OK;
 }
 
@@ -329,10 +333,13 @@ int rsa_create(rsa_ctx **out, int device, uint64_t hbm_budget_bytes, const rsa_a
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)p.totalGlobalMem);
     for (int t = 0; t < kNumWaveTiles; ++t) {
         for (int w = 0; w < 2; ++w) {
-            if (hipFuncSetAttribute(kPersistentKernels[t][w], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(c->lds_max - 64)) != hipSuccess) {
-                delete c;
-                return RSA_EDEVICE;
+            for (int sp = 0; sp < 2; ++sp) {
+                if (hipFuncSetAttribute(kPersistentKernels[t][w][sp],
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)(c->lds_max - 64)) != hipSuccess) {
+                    delete c;
+                    return RSA_EDEVICE;
+                }
             }
         }
     }
@@ -407,11 +414,11 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     b->mode = (int)c->opt_mode;
 
     // ---- plan: group by tile, longest samples first inside a group
-    // group key: wave count * 2 + (rows wider than 64 words)
+    // group key: (wave count, rows wider than 64 words, clear mode) -> kernel
     std::vector<int> tiles(n), keys(n);
     for (uint32_t i = 0; i < n; ++i) {
         tiles[i] = c->opt_tile >= 0 ? (int)c->opt_tile : default_tile(s[i].L, s[i].k);
-        keys[i] = tile_waves(tiles[i]) * 2 + (s[i].L > 4096 ? 1 : 0);
+        keys[i] = (tile_waves(tiles[i]) * 2 + (s[i].L > 4096 ? 1 : 0)) * 2 + tile_sparse(tiles[i]);
     }
     std::vector<uint32_t> order(n);
     for (uint32_t i = 0; i < n; ++i) order[i] = i;
@@ -422,15 +429,16 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     size_t total = 0;
     const size_t desc_bytes = align256((size_t)std::max<uint32_t>(n, 1) * sizeof(DevDesc));
     const size_t res_bytes = align256((size_t)std::max<uint32_t>(n, 1) * sizeof(DevResult));
-    const size_t queue_count = b->mode == RSA_MODE_PLAIN ? std::max<uint32_t>(n, 1) : 2 * kNumTiles;
+    const size_t queue_count = b->mode == RSA_MODE_PLAIN ? std::max<uint32_t>(n, 1) : 4 * kNumWaveTiles;
     const size_t queue_bytes = align256(queue_count * 4);
     const size_t prof_words = c->opt_prof ? (size_t)std::max<uint32_t>(n, 1) * kProfSlots : 0;
     const size_t prof_bytes = align256(prof_words * 8);
     total = desc_bytes + res_bytes + queue_bytes + prof_bytes;
     for (uint32_t i = 0; i < n;) {
         Group g;
-        g.waves = keys[order[i]] >> 1;
-        g.wide = keys[order[i]] & 1;
+        g.waves = keys[order[i]] >> 2;
+        g.wide = (keys[order[i]] >> 1) & 1;
+        g.sparse = keys[order[i]] & 1;
         g.first = i;
         uint32_t j = i;
         size_t stride = 0;
@@ -448,7 +456,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         if (b->mode == RSA_MODE_PLAIN) {
             grid = kPlainStreams;   // one slab per stream: samples on a stream run in order
         } else {
-            grid = std::min<uint32_t>(g.count, (uint32_t)resident_blocks(c, g.waves, g.wide, lds));
+            grid = std::min<uint32_t>(g.count, (uint32_t)resident_blocks(c, g.waves, g.wide, g.sparse, lds));
             if (c->opt_slots > 0) grid = std::min<uint32_t>(grid, (uint32_t)c->opt_slots);
         }
         g.grid = grid;
@@ -509,7 +517,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         a.descs = d_desc + g.first;
         a.n = g.count;
         a.tile = (uint32_t)g.waves;
-        a.queue = d_queue + g.waves * 2 + g.wide;
+        a.queue = d_queue + (g.waves * 2 + g.wide) * 2 + g.sparse;
         a.slabs = base + g.slab_off;
         a.slab_stride = g.stride;
         a.results = d_res;
@@ -541,7 +549,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
                 a.results = d_res;
                 a.prof = b->d_prof;
                 void *kargs[] = {&a};
-                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.waves][g.wide], dim3(1), dim3(threads), kargs,
+                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.waves][g.wide][g.sparse], dim3(1), dim3(threads), kargs,
                                            g.lds, c->plain[si]));
             }
         }
@@ -556,11 +564,11 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         for (size_t i = 0; i < args.size(); ++i) {
             const Group &g = b->groups[i];
             char buf[64];
-            std::snprintf(buf, sizeof(buf), "%d:%d:%u:%u|", g.waves, g.wide, g.grid, g.lds);
+            std::snprintf(buf, sizeof(buf), "%d:%d:%d:%u:%u|", g.waves, g.wide, g.sparse, g.grid, g.lds);
             key += buf;
             key.append((const char *)&args[i], sizeof(KernelArgs));
         }
-        uint32_t nq = 2 * kNumTiles;
+        uint32_t nq = 4 * kNumWaveTiles;
         if (c->opt_graph) {
             hipGraphExec_t exec = cached_graph(c, key);
             if (!exec) {
@@ -580,7 +588,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
                     hipKernelNodeParams kp;
                     std::memset(&kp, 0, sizeof(kp));
                     void *kargs[] = {&args[i]};
-                    kp.func = (void *)kPersistentKernels[g.waves][g.wide];
+                    kp.func = (void *)kPersistentKernels[g.waves][g.wide][g.sparse];
                     kp.gridDim = dim3(g.grid);
                     kp.blockDim = dim3(64 * (kTileWaves[g.waves] + 1));
                     kp.sharedMemBytes = g.lds;
@@ -604,7 +612,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
             for (size_t i = 0; i < args.size(); ++i) {
                 const Group &g = b->groups[i];
                 void *kargs[] = {&args[i]};
-                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.waves][g.wide], dim3(g.grid),
+                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.waves][g.wide][g.sparse], dim3(g.grid),
                                            dim3(64 * (kTileWaves[g.waves] + 1)), kargs, g.lds, stream));
             }
         }

@@ -35,6 +35,7 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
 // directions, so one slab size fits all tile shapes of a lattice.
 __host__ __device__ inline uint32_t padded_words(uint32_t L) { return ((L + 63) / 64 + 15) & ~15u; }
 __host__ __device__ inline uint32_t padded_side(uint32_t L) { return (L + 31) & ~31u; }
+__host__ __device__ inline uint32_t summary_words(uint32_t L) { return (padded_words(L) + 63) / 64; }
 
 // One sample as the kernels see it.
 struct DevDesc {
@@ -47,6 +48,8 @@ struct DevDesc {
     uint32_t lg_mr;    // site-map tile: 2^lg_mr rows x 2^(5-lg_mr) sites (128 B)
     uint32_t spec_rows;   // rows read ahead of each clear (power of two)
     uint32_t tile;        // schedule id reported in the result
+    uint32_t sparse;      // clear mode: 0 dense, 1 sparse (summary bits)
+    uint32_t pad1[3];
     FastDiv fL;        // division by L
     FastDiv fk;        // division by k
     FastDiv fC;        // division by 2k+2 (contacts per k-mer)
@@ -73,8 +76,11 @@ struct DevResult {
 //                       (dx, dy) = anchor minus the parent's anchor, unwrapped;
 //                       meta (roots only) = rank | wraps-in-x << 8 | -in-y << 9
 //   kmer                per k-mer anchor site index | orientation << 31
+//   sum[0], sum[1]      summary bits of the availability bitmaps, row-major:
+//                       bit w%64 of word w/64 of row y is set while word w
+//                       of row y may be non-zero (used by the sparse clear)
 struct SlabLayout {
-    size_t avail0, avail1, map, node, kmer, total;
+    size_t avail0, avail1, sum0, sum1, map, node, kmer, total;
 };
 
 __host__ __device__ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -87,6 +93,8 @@ __host__ __device__ inline SlabLayout slab_layout(uint32_t L, uint32_t k)
     size_t off = 0;
     s.avail0 = off; off = align256(off + lp * wp * 8);
     s.avail1 = off; off = align256(off + lp * wp * 8);
+    s.sum0 = off;   off = align256(off + lp * summary_words(L) * 8);   // summary bits, see below
+    s.sum1 = off;   off = align256(off + lp * summary_words(L) * 8);
     s.map = off;    off = align256(off + lp * lp * 4);
     s.node = off;   off = align256(off + cap * 16);
     s.kmer = off;   off = align256(off + cap * 4);
@@ -177,13 +185,17 @@ enum ProfSlot {
 // site-map tile height.  tile = waves + kNumWaveTiles * (lg_tr + 5 * lg_mr).
 constexpr int kNumWaveTiles = 5;
 constexpr int kTileWaves[kNumWaveTiles] = {1, 2, 3, 7, 15};   // + 1 labelling wave: <= 1024 threads
-constexpr int kNumTiles = kNumWaveTiles * 5 * 6;
+// The last dimension is the clear mode: 0 = dense (read every word of the
+// blocked rectangles), 1 = sparse (read the summary bits first and only the
+// words that are still non-zero).
+constexpr int kNumTiles = kNumWaveTiles * 5 * 6 * 2;
 __host__ __device__ inline int tile_waves(int tile) { return tile % kNumWaveTiles; }
 __host__ __device__ inline int tile_lg_tr(int tile) { return (tile / kNumWaveTiles) % 5; }
-__host__ __device__ inline int tile_lg_mr(int tile) { return tile / (kNumWaveTiles * 5); }
-__host__ __device__ inline int make_tile(int waves, int lg_tr, int lg_mr)
+__host__ __device__ inline int tile_lg_mr(int tile) { return (tile / (kNumWaveTiles * 5)) % 6; }
+__host__ __device__ inline int tile_sparse(int tile) { return tile / (kNumWaveTiles * 5 * 6); }
+__host__ __device__ inline int make_tile(int waves, int lg_tr, int lg_mr, int sparse = 0)
 {
-    return waves + kNumWaveTiles * (lg_tr + 5 * lg_mr);
+    return waves + kNumWaveTiles * (lg_tr + 5 * (lg_mr + 6 * sparse));
 }
 
 }  // namespace rsa

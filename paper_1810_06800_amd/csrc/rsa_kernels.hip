@@ -38,8 +38,7 @@ constexpr uint32_t kUnroll = 4;   // independent bitmap words in flight per lane
 // union-find); the sample then stops instead of reading out of bounds.
 constexpr int32_t kErrSelect = -100;
 constexpr int32_t kErrLabel = -101;
-constexpr uint32_t kMaxHops = 64;
-constexpr int kGather = 8;       // rounds of 64 contacts whose reads are in flight together   // union by rank keeps trees below log2(L^2) levels
+constexpr uint32_t kMaxHops = 64;   // union by rank keeps trees below log2(L^2) levels
 
 // ---------------------------------------------------------------------------
 // Small device helpers
@@ -181,6 +180,9 @@ struct Ctx {
     uint32_t spec_rows;
     FastDiv fL, fk, fC, fwd, fwp;
     uint64_t *av0, *av1;   // availability bitmaps of H / V placements
+    uint64_t *sm0, *sm1;   // their summary bits (sparse clear only)
+    uint32_t swp;          // summary words per row
+    uint32_t sparse;
     int32_t *map;
     int4 *node;
     uint32_t *kmer;
@@ -433,6 +435,127 @@ __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint3
     }
 }
 
+// Sparse clear of one rectangle.  Per row, the rectangle's words fall in one
+// or a few summary words (64 words each); an item is one (row, summary word).
+// A wave's lanes take CAP items at once: read their summary words, keep the
+// bits of the rectangle's words that may still be non-zero, then read only
+// those data words (up to DCAP in flight per lane per round), clear the
+// blocked bits, and drop the summary bit of every word that became zero.
+__device__ __forceinline__ uint32_t rect_summary_words(const Rect &r, uint32_t &nsA)
+{
+    nsA = ((r.a0 + r.nA - 1) >> 6) - (r.a0 >> 6) + 1;
+    const uint32_t nB = r.nw - r.nA;
+    return nsA + (nB ? ((nB - 1) >> 6) + 1 : 0);
+}
+
+template <int CAP, int DCAP>
+__device__ __forceinline__ void sparse_rect(const Ctx &c, const Rect &r, uint32_t wv, uint32_t nwv,
+                                            uint32_t &wchg)
+{
+    const uint32_t lane = lane_id(), L = c.L;
+    uint32_t nsA;
+    const uint32_t ns = rect_summary_words(r, nsA);
+    const uint32_t nB = r.nw - r.nA;
+    const uint32_t items = r.nrows * ns;
+    uint64_t *const bm = bitmap(c, r.o);
+    uint64_t *const sm = r.o ? c.sm1 : c.sm0;
+    const uint32_t rowbase = r.o * L;
+    for (uint32_t base = wv * 64; base < items; base += nwv * 64 * CAP) {
+        uint64_t cand[CAP], zero[CAP];
+        uint32_t srow[CAP], ssw[CAP];
+#pragma unroll
+        for (int s = 0; s < CAP; ++s) {
+            const uint32_t f = base + (uint32_t)s * nwv * 64 + lane;
+            uint64_t bits = 0;
+            uint32_t row = 0, sw = 0;
+            if (f < items) {
+                const uint32_t i = f / ns, j = f - i * ns;
+                row = r.row0 + i;
+                row = row >= L ? row - L : row;
+                uint32_t lo, hi;   // data words of this item, [lo, hi)
+                if (j < nsA) {
+                    sw = (r.a0 >> 6) + j;
+                    lo = sw * 64 > r.a0 ? sw * 64 : r.a0;
+                    hi = sw * 64 + 64 < r.a0 + r.nA ? sw * 64 + 64 : r.a0 + r.nA;
+                } else {
+                    sw = j - nsA;
+                    lo = sw * 64;
+                    hi = sw * 64 + 64 < nB ? sw * 64 + 64 : nB;
+                }
+                const uint32_t b0 = lo - sw * 64, b1 = hi - sw * 64;
+                bits = (b1 == 64 ? ~0ull : ((1ull << b1) - 1)) & ~((1ull << b0) - 1);
+            }
+            srow[s] = row;
+            ssw[s] = sw;
+            cand[s] = bits;
+            zero[s] = 0;
+        }
+#pragma unroll
+        for (int s = 0; s < CAP; ++s)
+            if (cand[s]) cand[s] &= sm[(size_t)srow[s] * c.swp + ssw[s]];
+        // data words, DCAP per lane per round
+        for (;;) {
+            bool any = false;
+#pragma unroll
+            for (int s = 0; s < CAP; ++s) any = any || cand[s] != 0;
+            if (__ballot(any) == 0) break;
+            uint64_t old[DCAP];
+            uint32_t pick[DCAP];   // item << 8 | word bit, or ~0
+#pragma unroll
+            for (int d = 0; d < DCAP; ++d) {
+                pick[d] = 0xFFFFFFFFu;
+                old[d] = 0;
+#pragma unroll
+                for (int s = 0; s < CAP; ++s) {
+                    if (pick[d] == 0xFFFFFFFFu && cand[s] != 0) {
+                        const uint32_t b = (uint32_t)(__ffsll((long long)cand[s]) - 1);
+                        cand[s] &= cand[s] - 1;
+                        pick[d] = ((uint32_t)s << 8) | b;
+                        old[d] = bm[bm_index(c, srow[s], ssw[s] * 64 + b)];
+                    }
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < DCAP; ++d) {
+                if (pick[d] == 0xFFFFFFFFu) continue;
+                const uint32_t s = pick[d] >> 8, b = pick[d] & 255u;
+                uint32_t row = 0, sw = 0;
+#pragma unroll
+                for (int q = 0; q < CAP; ++q)
+                    if ((uint32_t)q == s) {
+                        row = srow[q];
+                        sw = ssw[q];
+                    }
+                const uint32_t w = sw * 64 + b;
+                const uint64_t hit = old[d] & col_mask(L, r.c0, r.len, w);
+                if (hit) {
+                    const uint64_t nv = old[d] & ~hit;
+                    bm[bm_index(c, row, w)] = nv;
+                    count_sub(c, rowbase + row, (uint32_t)__popcll(hit));
+                    ++wchg;
+                    if (nv == 0) {
+#pragma unroll
+                        for (int q = 0; q < CAP; ++q)
+                            if ((uint32_t)q == s) zero[q] |= 1ull << b;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < CAP; ++s)
+            if (zero[s]) atomicAnd((unsigned long long *)&sm[(size_t)srow[s] * c.swp + ssw[s]], ~zero[s]);
+    }
+}
+
+template <int CAP>
+__device__ __forceinline__ void sparse_clear(const Ctx &c, const Clear &cl, uint32_t wv, uint32_t nwv,
+                                             uint32_t &wchg)
+{
+    (void)CAP;   // four summary words and eight data words in flight per lane
+    sparse_rect<4, 8>(c, cl.a, wv, nwv, wchg);
+    sparse_rect<4, 8>(c, cl.b, wv, nwv, wchg);
+}
+
 // Words a lane holds of one bitmap row: lane, lane+64, ... (ROWW of them;
 // ROWW = 1 covers L <= 4096, 8 covers L <= 32768).
 template <int ROWW>
@@ -643,11 +766,13 @@ struct TileCap {
 // Selecting wave
 // ---------------------------------------------------------------------------
 
-template <int NSEL, int ROWW>
+template <int NSEL, int ROWW, bool SPARSE>
 __device__ __forceinline__ void selector(Ctx &c)
 {
     constexpr int CAP = TileCap<NSEL>::value;
-    constexpr int SPW = ROWW == 1 ? 2 : 8;
+    // read-ahead window (words per lane); for rows wider than 64 words the
+    // window covers too few rows to hit often, so it is left out
+    constexpr int SPW = ROWW == 1 ? 2 : 0;
     const uint32_t lane = lane_id();
     __builtin_amdgcn_s_setprio(2);   // latency-critical chain first on a shared SIMD
     const uint32_t L = c.L, k = c.k;
@@ -719,15 +844,19 @@ __device__ __forceinline__ void selector(Ctx &c)
         // read the rows where step t+1 will most likely pick, then clear:
         // the clear's reads are issued after the read-ahead's, so waiting for
         // them covers both
-        SpecRows<SPW> sp;
+        SpecRows<SPW == 0 ? 1 : SPW> sp;
+        sp.nr = 0;
         uint64_t ph = prof ? tick() : 0;
-        read_ahead<SPW>(c, cl, u1, sp);
+        if constexpr (SPW > 0) read_ahead<SPW>(c, cl, u1, sp);
         if (prof) {
             uint64_t ph1 = tick();
             p_hook += ph1 - ph;
             ph = ph1;
         }
-        clear_items<CAP>(c, cl, 0, NSEL, wchg);
+        if constexpr (SPARSE)
+            sparse_clear<CAP>(c, cl, 0, NSEL, wchg);
+        else
+            clear_items<CAP>(c, cl, 0, NSEL, wchg);
         if (prof) p_proc += tick() - ph;
         if (NSEL > 1) {
             // helpers' bitmap stores must be visible before the next select
@@ -751,8 +880,8 @@ __device__ __forceinline__ void selector(Ctx &c)
         }
         RowWords<ROWW> rw;
         const uint32_t ro = R >= L ? 1u : 0u, ry = R - ro * L;
-        if (sp.nr && ro == sp.o && ry >= sp.y0 && ry < sp.y0 + sp.nr) {
-            row_from_window<SPW, ROWW>(c, sp, ry, rw);
+        if (SPW > 0 && sp.nr && ro == sp.o && ry >= sp.y0 && ry < sp.y0 + sp.nr) {
+            row_from_window<SPW == 0 ? 1 : SPW, ROWW>(c, sp, ry, rw);
             patch_row(c, cl, R, rw);
             ++spec_hits;
         } else {
@@ -784,7 +913,7 @@ __device__ __forceinline__ void selector(Ctx &c)
     }
 }
 
-template <int NSEL>
+template <int NSEL, bool SPARSE>
 __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
 {
     constexpr int CAP = TileCap<NSEL>::value;
@@ -812,7 +941,10 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
         uint32_t y = fdiv(rem, c.fL);
         uint32_t x = rem - y * c.L;
         const Clear cl = make_clear(c, o, y, x);
-        clear_items<CAP>(c, cl, wv, NSEL, wchg);
+        if constexpr (SPARSE)
+            sparse_clear<CAP>(c, cl, wv, NSEL, wchg);
+        else
+            clear_items<CAP>(c, cl, wv, NSEL, wchg);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (lane == 0) atomicAdd(&c.h->clr_done, 1u);
     }
@@ -878,9 +1010,57 @@ __device__ __forceinline__ uint32_t local_find(const Ctx &c, uint32_t a, int32_t
     return x;
 }
 
+// Contact q of a batch starting at deposit tl: deposit m = tl + q / (2k+2),
+// index ci of the contact along it, the site ii of m it touches, the unit
+// step e and the neighbouring site b = anchor_m + ii * u_m + e (mod L).
+struct Contact {
+    bool act;
+    uint32_t m, ci, bx, by;
+    int32_t ii, ex, ey, umx, umy;
+};
+
+__device__ __forceinline__ Contact contact_of(const Ctx &c, uint32_t tl, uint32_t q, uint32_t total)
+{
+    const uint32_t L = c.L, k = c.k;
+    Contact ct;
+    ct.act = q < total;
+    const uint32_t i = ct.act ? fdiv(q, c.fC) : 0;
+    ct.ci = q - i * (2 * k + 2);
+    ct.m = tl + i;
+    const uint32_t am = c.banc[i];
+    const uint32_t om = am >> 31, site = am & 0x7FFFFFFFu;
+    const uint32_t ay = fdiv(site, c.fL), ax = site - ay * L;
+    ct.umx = om ? 0 : 1;
+    ct.umy = om ? 1 : 0;
+    if (ct.ci < k) {
+        ct.ii = (int32_t)ct.ci;
+        ct.ex = om ? -1 : 0;
+        ct.ey = om ? 0 : -1;
+    } else if (ct.ci < 2 * k) {
+        ct.ii = (int32_t)(ct.ci - k);
+        ct.ex = om ? 1 : 0;
+        ct.ey = om ? 0 : 1;
+    } else if (ct.ci == 2 * k) {
+        ct.ii = 0;
+        ct.ex = -ct.umx;
+        ct.ey = -ct.umy;
+    } else {
+        ct.ii = (int32_t)k - 1;
+        ct.ex = ct.umx;
+        ct.ey = ct.umy;
+    }
+    int32_t bx = (int32_t)ax + ct.ii * ct.umx + ct.ex, by = (int32_t)ay + ct.ii * ct.umy + ct.ey;
+    bx = bx >= (int32_t)L ? bx - (int32_t)L : (bx < 0 ? bx + (int32_t)L : bx);
+    by = by >= (int32_t)L ? by - (int32_t)L : (by < 0 ? by + (int32_t)L : by);
+    ct.bx = (uint32_t)bx;
+    ct.by = (uint32_t)by;
+    return ct;
+}
+
 struct LabelState {
     uint32_t base;   // k-mers base .. base+nb-1 own slots 0 .. nb-1
     uint32_t nb;
+    uint32_t tl;     // first deposit of the batch (anchors in banc[n - tl])
     int32_t nx, ny;
 };
 
@@ -989,18 +1169,31 @@ __device__ __forceinline__ void process_chunk(const Ctx &c, LabelState &ls, uint
         reset_slots(c, ls);
         __builtin_amdgcn_wave_barrier();
     }
+    const uint32_t L = c.L, nC = 2 * c.k + 2;
     for (uint32_t e0 = 0; e0 < ne; e0 += 64) {
         uint32_t e = e0 + lane;
         bool act = e < ne;
         uint32_t m = act ? c.e_step[e] : 0;
         uint32_t n = act ? c.e_ms[e] : 0;
+        // the neighbour's anchor (read now, used after the finds)
+        uint32_t an = 0;
+        if (act) an = n >= ls.tl ? c.banc[n - ls.tl] : c.kmer[n];
         int32_t dmx, dmy, dnx, dny;
         uint32_t sm = resolve_slot(c, ls, act, m, dmx, dmy);
         uint32_t sn = resolve_slot(c, ls, act, n, dnx, dny);
         if (act) {
+            // v = anchor_m - anchor_n through this contact, unwrapped
+            const Contact ct = contact_of(c, ls.tl, (m - ls.tl) * nC + (uint32_t)c.e_vx[e], 0xFFFFFFFFu);
+            const uint32_t on = an >> 31, ns = an & 0x7FFFFFFFu;
+            const uint32_t ny_ = fdiv(ns, c.fL), nx_ = ns - ny_ * L;
+            int32_t j = on ? (int32_t)ct.by - (int32_t)ny_ : (int32_t)ct.bx - (int32_t)nx_;
+            j = j < 0 ? j + (int32_t)L : j;
+            const int32_t unx = on ? 0 : 1, uny = on ? 1 : 0;
+            const int32_t vx = j * unx - ct.ii * ct.umx - ct.ex;
+            const int32_t vy = j * uny - ct.ii * ct.umy - ct.ey;
             c.e_ms[e] = sm | (sn << 16);
-            c.e_vx[e] += dnx - dmx;
-            c.e_vy[e] += dny - dmy;
+            c.e_vx[e] = vx + dnx - dmx;
+            c.e_vy[e] = vy + dny - dmy;
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -1047,53 +1240,7 @@ __device__ __forceinline__ void process_chunk(const Ctx &c, LabelState &ls, uint
     if (prof) prof_add(c, kProfLabMerge, tick() - p0);
 }
 
-// Contact q of a batch starting at deposit tl: deposit m = tl + q / (2k+2),
-// index ci of the contact along it, the site ii of m it touches, the unit
-// step e and the neighbouring site b = anchor_m + ii * u_m + e (mod L).
-struct Contact {
-    bool act;
-    uint32_t m, ci, bx, by;
-    int32_t ii, ex, ey, umx, umy;
-};
-
-__device__ __forceinline__ Contact contact_of(const Ctx &c, uint32_t tl, uint32_t q, uint32_t total)
-{
-    const uint32_t L = c.L, k = c.k;
-    Contact ct;
-    ct.act = q < total;
-    const uint32_t i = ct.act ? fdiv(q, c.fC) : 0;
-    ct.ci = q - i * (2 * k + 2);
-    ct.m = tl + i;
-    const uint32_t am = c.banc[i];
-    const uint32_t om = am >> 31, site = am & 0x7FFFFFFFu;
-    const uint32_t ay = fdiv(site, c.fL), ax = site - ay * L;
-    ct.umx = om ? 0 : 1;
-    ct.umy = om ? 1 : 0;
-    if (ct.ci < k) {
-        ct.ii = (int32_t)ct.ci;
-        ct.ex = om ? -1 : 0;
-        ct.ey = om ? 0 : -1;
-    } else if (ct.ci < 2 * k) {
-        ct.ii = (int32_t)(ct.ci - k);
-        ct.ex = om ? 1 : 0;
-        ct.ey = om ? 0 : 1;
-    } else if (ct.ci == 2 * k) {
-        ct.ii = 0;
-        ct.ex = -ct.umx;
-        ct.ey = -ct.umy;
-    } else {
-        ct.ii = (int32_t)k - 1;
-        ct.ex = ct.umx;
-        ct.ey = ct.umy;
-    }
-    int32_t bx = (int32_t)ax + ct.ii * ct.umx + ct.ex, by = (int32_t)ay + ct.ii * ct.umy + ct.ey;
-    bx = bx >= (int32_t)L ? bx - (int32_t)L : (bx < 0 ? bx + (int32_t)L : bx);
-    by = by >= (int32_t)L ? by - (int32_t)L : (by < 0 ? by + (int32_t)L : by);
-    ct.bx = (uint32_t)bx;
-    ct.by = (uint32_t)by;
-    return ct;
-}
-
+template <int G>
 __device__ __forceinline__ void labeler(Ctx &c, bool track)
 {
     const uint32_t lane = lane_id();
@@ -1163,73 +1310,54 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track)
         }
         ls.base = tl;
         ls.nb = B;
+        ls.tl = tl;
         reset_slots(c, ls);
         __builtin_amdgcn_wave_barrier();
         // contacts of every deposit of the batch, in deposit order:
         // c in [0,k): above (H) / left (V) of site c; [k,2k): below / right;
-        // 2k: before site 0; 2k+1: after site k-1.  kGather rounds of 64
-        // contacts have their map reads in flight together, then their
-        // k-mer record reads, then are compacted in order.
+        // 2k: before site 0; 2k+1: after site k-1.  G rounds of 64 contacts
+        // have their map reads in flight together.  A contact with the same
+        // neighbour as the previous one on the same side has the same vector
+        // v (their offsets along both k-mers move together) unless k = L,
+        // where a run can pass the seam; such repeats are dropped.  The
+        // edge keeps the contact index; v is formed once the neighbour's
+        // anchor has been read, next to the cluster finds.
         uint32_t ne = 0;
-        int32_t cn = -1, cvx = 0, cvy = 0;
+        int32_t cn = -1;
         const uint32_t total = B * nC;
+        const bool dedupe = k != L;
         bool stop = false;
-        for (uint32_t g0 = 0; g0 < total && !stop; g0 += 64 * kGather) {
-            int32_t nval[kGather];
-            uint32_t aval[kGather];
+        for (uint32_t g0 = 0; g0 < total && !stop; g0 += 64 * G) {
+            int32_t nval[G];
 #pragma unroll
-            for (int g = 0; g < kGather; ++g) {
+            for (int g = 0; g < G; ++g) {
                 Contact ct = contact_of(c, tl, g0 + 64 * g + lane, total);
                 nval[g] = ct.act ? c.map[map_index(c, ct.by, ct.bx)] : -1;
             }
 #pragma unroll
-            for (int g = 0; g < kGather; ++g) {
-                uint32_t m = tl + fdiv(g0 + 64 * g + lane, fC);
-                int32_t n = nval[g];
-                bool keep = n >= 0 && (uint32_t)n <= m;
-                aval[g] = 0;
-                if (keep) aval[g] = (uint32_t)n >= tl ? c.banc[(uint32_t)n - tl] : c.kmer[n];
-            }
-#pragma unroll
-            for (int g = 0; g < kGather; ++g) {
+            for (int g = 0; g < G; ++g) {
                 const uint32_t q0 = g0 + 64 * g;
                 if (q0 >= total || stop) continue;
-                Contact ct = contact_of(c, tl, q0 + lane, total);
-                int32_t n = nval[g];
-                bool keep = ct.act && n >= 0 && (uint32_t)n <= ct.m;
-                int32_t vx = 0, vy = 0;
-                if (keep) {
-                    uint32_t an = aval[g];
-                    uint32_t on = an >> 31, ns = an & 0x7FFFFFFFu;
-                    uint32_t ny_ = fdiv(ns, c.fL), nx_ = ns - ny_ * L;
-                    int32_t j = on ? (int32_t)ct.by - (int32_t)ny_ : (int32_t)ct.bx - (int32_t)nx_;
-                    j = j < 0 ? j + (int32_t)L : j;
-                    int32_t unx = on ? 0 : 1, uny = on ? 1 : 0;
-                    // v = anchor_m - anchor_n through this contact, unwrapped
-                    vx = j * unx - ct.ii * ct.umx - ct.ex;
-                    vy = j * uny - ct.ii * ct.umy - ct.ey;
-                }
-                // drop a contact equal to the previous one on the same side
-                int32_t key = keep ? n : -1;
-                int32_t pn = __shfl_up(key, 1, 64), pvx = __shfl_up(vx, 1, 64), pvy = __shfl_up(vy, 1, 64);
-                if (lane == 0) {
-                    pn = cn;
-                    pvx = cvx;
-                    pvy = cvy;
-                }
-                bool same_run = ct.ci > 0 && ct.ci < 2 * k && ct.ci != k;
-                bool emit = keep && !(same_run && pn == n && pvx == vx && pvy == vy);
+                const uint32_t q = q0 + lane;
+                const bool act = q < total;
+                const uint32_t i = act ? fdiv(q, fC) : 0;
+                const uint32_t ci = q - i * nC;
+                const uint32_t m = tl + i;
+                const int32_t n = nval[g];
+                const bool keep = act && n >= 0 && (uint32_t)n <= m;
+                const int32_t key = keep ? n : -1;
+                int32_t pn = __shfl_up(key, 1, 64);
+                if (lane == 0) pn = cn;
+                const bool same_run = ci > 0 && ci < 2 * k && ci != k;
+                const bool emit = keep && !(dedupe && same_run && pn == n);
                 cn = (int32_t)bcast((uint32_t)key, 63);
-                cvx = (int32_t)bcast((uint32_t)vx, 63);
-                cvy = (int32_t)bcast((uint32_t)vy, 63);
                 uint64_t bal = __ballot(emit);
                 uint32_t off = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
                 if (emit) {
                     uint32_t idx = ne + off;
-                    c.e_step[idx] = ct.m;
+                    c.e_step[idx] = m;
                     c.e_ms[idx] = (uint32_t)n;
-                    c.e_vx[idx] = vx;
-                    c.e_vy[idx] = vy;
+                    c.e_vx[idx] = (int32_t)ci;
                 }
                 ne += (uint32_t)__popcll(bal);
                 __builtin_amdgcn_wave_barrier();
@@ -1303,6 +1431,10 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
     SlabLayout s = slab_layout(d.L, d.k);
     c.av0 = (uint64_t *)(slab + s.avail0);
     c.av1 = (uint64_t *)(slab + s.avail1);
+    c.sm0 = (uint64_t *)(slab + s.sum0);
+    c.sm1 = (uint64_t *)(slab + s.sum1);
+    c.swp = summary_words(d.L);
+    c.sparse = d.sparse;
     c.map = (int32_t *)(slab + s.map);
     c.node = (int4 *)(slab + s.node);
     c.kmer = (uint32_t *)(slab + s.kmer);
@@ -1328,7 +1460,7 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
     c.h_val = c.h_key + kHash;
 }
 
-template <int NSEL, int ROWW>
+template <int NSEL, int ROWW, bool SPARSE>
 __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d, uint8_t *lds)
 {
     constexpr uint32_t NT = 64 * (NSEL + 1);
@@ -1359,6 +1491,17 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             size_t at = bm_index(c, row, wi);
             c.av0[at] = full;
             c.av1[at] = h_only ? 0ull : full;
+        }
+        if (SPARSE) {
+            // summary bit set for every word of a real row and column
+            const uint32_t nsum = c.lp * c.swp;
+            for (uint32_t i = tid; i < nsum; i += NT) {
+                uint32_t row = i / c.swp, sw = i - row * c.swp;
+                uint32_t lo = sw * 64, hi = lo + 64 < wd ? lo + 64 : wd;
+                uint64_t bits = (row >= L || lo >= wd) ? 0ull : (hi - lo == 64 ? ~0ull : ((1ull << (hi - lo)) - 1));
+                c.sm0[i] = bits;
+                c.sm1[i] = h_only ? 0ull : bits;
+            }
         }
         const uint32_t rows = 2 * L;
         const uint32_t vcount = h_only ? 0u : L;
@@ -1403,11 +1546,11 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
 
     // ---- the two chains
     if (wave == 0)
-        selector<NSEL, ROWW>(c);
+        selector<NSEL, ROWW, SPARSE>(c);
     else if (wave < (uint32_t)NSEL)
-        helper<NSEL>(c, wave);
+        helper<NSEL, SPARSE>(c, wave);
     else
-        labeler(c, track);
+        labeler<(NSEL >= 7 ? 16 : 8)>(c, track);
     __syncthreads();
 
     // ---- cluster census at jamming (Appendix A)
@@ -1449,7 +1592,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
     __syncthreads();
 }
 
-template <int NSEL, int ROWW>
+template <int NSEL, int ROWW, bool SPARSE>
 __global__ __launch_bounds__(64 * (NSEL + 1)) void rsa_persistent(KernelArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -1461,7 +1604,7 @@ __global__ __launch_bounds__(64 * (NSEL + 1)) void rsa_persistent(KernelArgs a)
         __syncthreads();
         if (i >= a.n) return;
         const DevDesc d = a.descs[i];
-        run_sample<NSEL, ROWW>(a, d, lds);
+        run_sample<NSEL, ROWW, SPARSE>(a, d, lds);
     }
 }
 
@@ -1473,14 +1616,14 @@ __global__ void rsa_reset_queues(uint32_t *queues, uint32_t n)
 
 }  // namespace rsa
 
-// Host-visible launch table: [tile][row words per lane 1 or 8].
+// Host-visible launch table: [tile waves][row words per lane 1 or 8][dense, sparse].
 namespace rsa {
-extern const void *kPersistentKernels[kNumWaveTiles][2];
-const void *kPersistentKernels[kNumWaveTiles][2] = {
-    {(const void *)&rsa_persistent<kTileWaves[0], 1>, (const void *)&rsa_persistent<kTileWaves[0], 8>},
-    {(const void *)&rsa_persistent<kTileWaves[1], 1>, (const void *)&rsa_persistent<kTileWaves[1], 8>},
-    {(const void *)&rsa_persistent<kTileWaves[2], 1>, (const void *)&rsa_persistent<kTileWaves[2], 8>},
-    {(const void *)&rsa_persistent<kTileWaves[3], 1>, (const void *)&rsa_persistent<kTileWaves[3], 8>},
-    {(const void *)&rsa_persistent<kTileWaves[4], 1>, (const void *)&rsa_persistent<kTileWaves[4], 8>}};
+#define RSA_K(W) {{(const void *)&rsa_persistent<kTileWaves[W], 1, false>,   \
+                   (const void *)&rsa_persistent<kTileWaves[W], 1, true>},   \
+                  {(const void *)&rsa_persistent<kTileWaves[W], 8, false>,   \
+                   (const void *)&rsa_persistent<kTileWaves[W], 8, true>}}
+extern const void *kPersistentKernels[kNumWaveTiles][2][2];
+const void *kPersistentKernels[kNumWaveTiles][2][2] = {RSA_K(0), RSA_K(1), RSA_K(2), RSA_K(3), RSA_K(4)};
+#undef RSA_K
 const void *kResetKernel = (const void *)&rsa_reset_queues;
 }  // namespace rsa

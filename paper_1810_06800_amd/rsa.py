@@ -105,7 +105,7 @@ def lib() -> ctypes.CDLL:
     L.rsa_tile_for_shape.argtypes = [u32, u32]
     L.rsa_tile_for_shape.restype = i32
     ip = ctypes.POINTER(ctypes.c_int)
-    L.rsa_tile_shape.argtypes = [i32, ip, ip, ip]
+    L.rsa_tile_shape.argtypes = [i32, ip, ip, ip, ip]
     L.rsa_tile_shape.restype = i32
     _lib = L
     return L
@@ -127,13 +127,13 @@ def tile_for_shape(L: int, k: int) -> int:
     return lib().rsa_tile_for_shape(L, k)
 
 
-def tile_shape(tile: int) -> tuple[int, int, int]:
-    """(waves sharing select/clear, bitmap tile rows, map tile rows)."""
-    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    rc = lib().rsa_tile_shape(tile, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+def tile_shape(tile: int) -> tuple[int, int, int, int]:
+    """(waves sharing select/clear, bitmap tile rows, map tile rows, sparse clear)."""
+    a, b, c, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    rc = lib().rsa_tile_shape(tile, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d))
     if rc != RSA_OK:
         raise RsaError(rc, "rsa_tile_shape")
-    return a.value, b.value, c.value
+    return a.value, b.value, c.value, d.value
 
 
 def make_samples(descs: Iterable[Sequence[int]]):

@@ -44,7 +44,8 @@ def test_footprint_matches_layout(rsa):
         wp = ((L + 63) // 64 + 15) // 16 * 16
         lp = (L + 31) // 32 * 32
         cap = L * L // k + 1
-        return a(lp * wp * 8) * 2 + a(4 * lp * lp) + a(16 * cap) + a(4 * cap)
+        summary = a(lp * ((wp + 63) // 64) * 8)
+        return a(lp * wp * 8) * 2 + summary * 2 + a(4 * lp * lp) + a(16 * cap) + a(4 * cap)
 
     for L, k in [(1, 1), (5, 3), (64, 8), (1024, 64), (16384, 1024), (32768, 4096)]:
         assert rsa.footprint_bytes(L, k) == expect(L, k)
@@ -65,8 +66,9 @@ def test_strerror_and_tiles(rsa):
     assert rsa.tile_for_shape(4, 5) == rsa.RSA_EINVAL
     shapes = {rsa.tile_shape(t) for t in range(n)}
     assert len(shapes) == n
-    for waves, tr, mr in shapes:
+    for waves, tr, mr, sparse in shapes:
         assert 1 <= waves <= 15 and tr in (1, 2, 4, 8, 16) and mr in (1, 2, 4, 8, 16, 32)
+        assert sparse in (0, 1)
         assert 64 * (waves + 1) <= 1024
     with pytest.raises(rsa.RsaError):
         rsa.tile_shape(n)
