@@ -214,6 +214,85 @@ int rsa_num_tiles(void);
 int rsa_tile_for_shape(uint32_t L, uint32_t k);
 int rsa_tile_shape(int tile, int *waves, int *bitmap_tile_rows, int *map_tile_rows, int *sparse);
 
+/* ---------------------------------------------------------------------------
+ * Request server: continuous batching of independent runs (Sec. II.A: every
+ * sample is one run of the problem above) submitted over time.
+ *
+ * Each sample of an admitted request gets its own device state (bitmaps, site
+ * map, k-mer records: rsa_footprint_bytes) carved from an arena that the
+ * server allocates once, and keeps it resident until it jams.  The device
+ * runs in launches of one time quantum: every resident sample that a
+ * workgroup reaches advances until the quantum is spent, then saves its row
+ * counts and chain position next to its lattice and yields; the next launch
+ * resumes it exactly there.  Between launches the host retires finished
+ * samples (their arena space is reused) and admits queued samples, oldest
+ * request first, as arena space and resident slots free up, so new requests
+ * join work already on the device.  Results are the same, bit for bit, as
+ * rsa_run_batch's for the same descriptors, whatever else runs beside them.
+ *
+ * Two launches are kept in flight on the server's streams (forked from and
+ * joined to the caller's stream), so the device never waits for the host's
+ * bookkeeping.  A server is used from one host thread at a time, like its
+ * context, and the context must outlive it.
+ * ------------------------------------------------------------------------- */
+typedef struct rsa_server rsa_server;
+
+typedef struct {
+    uint64_t arena_bytes;    /* device bytes for resident samples; 0 = half of the
+                                context's budget                                  */
+    uint32_t quantum_us;     /* device time per launch before samples yield;
+                                0 = 2000 us                                       */
+    uint32_t max_resident;   /* samples resident at once; 0 = 4096                */
+} rsa_server_config_t;
+
+typedef struct {
+    uint64_t requests_submitted, requests_completed;
+    uint64_t samples_queued;     /* submitted, not yet admitted                       */
+    uint64_t samples_resident;   /* admitted, not yet retired                         */
+    uint64_t samples_completed;
+    uint64_t deposits_completed; /* n_jam summed over completed samples               */
+    uint64_t arena_bytes, arena_used, arena_peak;
+    uint64_t launches;
+} rsa_server_stats_t;
+
+/* Create a server on `ctx` whose launches are ordered after work already on
+ * `hip_stream` (a hipStream_t, NULL = null stream).  cfg NULL = defaults.
+ * RSA_ENOMEM if the arena does not fit the context's budget, RSA_EINVAL for a
+ * NULL ctx or out, RSA_EDEVICE on a HIP failure. */
+int rsa_server_create(rsa_ctx *ctx, const rsa_server_config_t *cfg, void *hip_stream,
+                      rsa_server **out);
+
+/* Queue a request of n samples (copied; the caller keeps `samples`) and
+ * return its id in *request_id.  Nothing is launched here; rsa_server_step
+ * admits and runs.  RSA_EINVAL (nothing queued) for n == 0, an invalid
+ * descriptor, or one whose row counts do not fit a workgroup's LDS;
+ * RSA_ENOMEM if one sample alone needs more than the arena. */
+int rsa_server_submit(rsa_server *srv, const rsa_sample_t *samples, uint32_t n,
+                      uint64_t *request_id);
+
+/* One round of the loop: retire launches that finished (wait = 1: block
+ * until at least one has, when any is in flight), admit queued samples that
+ * fit, and enqueue launches until two are in flight.  Returns the number of
+ * requests that completed during the call (>= 0), or a negative status. */
+int rsa_server_step(rsa_server *srv, int wait);
+
+/* Ids of completed requests not yet reported by this call, oldest first: up
+ * to `cap` are written to ids; returns how many were written. */
+int rsa_server_completed(rsa_server *srv, uint64_t *ids, uint32_t cap);
+
+/* Copy the n results of a completed request (descriptor order) and forget
+ * it.  RSA_ENOTREADY if it has not completed (it stays queued or running),
+ * RSA_ENOTFOUND for an unknown or already collected id, RSA_EINVAL if n
+ * differs from the request's size. */
+int rsa_server_results(rsa_server *srv, uint64_t request_id, rsa_result_t *out, uint32_t n);
+
+/* Counters of the server so far. */
+int rsa_server_stats(rsa_server *srv, rsa_server_stats_t *out);
+
+/* Wait for the launches in flight, drop queued and resident samples, and
+ * free the arena and the server.  NULL is ignored. */
+void rsa_server_destroy(rsa_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

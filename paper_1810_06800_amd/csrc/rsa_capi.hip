@@ -5,92 +5,19 @@
 // and all groups of a batch run as parallel nodes of one hipGraph (instantiated
 // once per launch signature and replayed).  Device memory comes from a
 // per-context pool of slabs, through the caller's allocator when one is given.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cstdio>
-#include <cstring>
-#include <map>
-#include <memory>
-#include <new>
-#include <string>
-#include <vector>
-
-#include "../../include/rsa.h"
-#include "rsa_device.h"
+#include "rsa_runtime.h"
 
 namespace rsa {
-extern const void *kPersistentKernels[kNumWaveTiles][2][2];
-extern const void *kResetKernel;
-}  // namespace rsa
 
-using namespace rsa;
-
-static_assert(sizeof(rsa_result_t) == sizeof(DevResult), "result layout");
-static_assert(sizeof(rsa_result_t) == 80, "result size");
-static_assert(sizeof(rsa_sample_t) == 24, "sample size");
-
-namespace {
-
-constexpr int kPlainStreams = 4;
-
-struct Group {
-    int waves;               // index into kTileWaves (the kernel instantiation)
-    int wide;                // rows of more than 64 words (L > 4096)
-    int sparse;              // clear mode
-    uint32_t first, count;   // range in the planned descriptor array
-    uint32_t grid;
-    uint32_t lds;
-    size_t stride;           // slab bytes per resident workgroup
-    size_t slab_off;         // offset of this group's slabs in the batch allocation
-};
-
-struct Block {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-};
-
-struct Batch {
-    uint64_t id = 0;
-    uint32_t n = 0;
-    Block mem;
-    DevDesc *h_desc = nullptr;      // pinned
-    rsa_result_t *h_res = nullptr;  // pinned
-    hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_done = nullptr;
-    std::vector<Group> groups;
-    int mode = RSA_MODE_BATCHED;
-    unsigned long long *d_prof = nullptr;   // inside mem, or null
-};
-
-struct GraphEntry {
-    std::string key;
-    hipGraphExec_t exec = nullptr;
-};
-
-}  // namespace
-
-struct rsa_ctx {
-    int device = 0;
-    int cus = 0;
-    size_t lds_max = 0;
-    uint64_t budget = 0;
-    uint64_t held = 0;   // bytes currently allocated (in use + pooled)
-    bool custom = false;
-    rsa_allocator_t alloc{};
-    bool poisoned = false;
-    std::string last_error;
-    uint64_t next_id = 1;
-    std::map<uint64_t, Batch *> batches;
-    std::vector<Block> pool;   // free device blocks
-    std::vector<GraphEntry> graphs;
-    int64_t opt_mode = RSA_MODE_BATCHED, opt_tile = -1, opt_graph = 1, opt_slots = 0, opt_prof = 0;
-    int clock_khz = 0;
-    hipStream_t plain[kPlainStreams] = {};
-    hipEvent_t fork = nullptr, join[kPlainStreams] = {};
-    int resident[kNumTiles][4] = {};   // cached occupancy per tile and LDS class
-};
-
-namespace {
+// persistent kernel of a schedule: (wave-count index, rows wider than 64
+// words, sparse clear)
+const void *persistent_kernel(int waves, int wide, int sparse)
+{
+    static const void *(*const tables[kNumWaveTiles])[2] = {
+        kPersistentKernelsW0, kPersistentKernelsW1, kPersistentKernelsW2, kPersistentKernelsW3,
+        kPersistentKernelsW4};
+    return tables[waves][wide][sparse];
+}
 
 int fail(rsa_ctx *c, int code, const std::string &msg)
 {
@@ -106,12 +33,6 @@ int hip_fail(rsa_ctx *c, hipError_t e, const char *what)
     }
     return RSA_EDEVICE;
 }
-
-#define HIP_TRY(ctx, expr)                                  \
-    do {                                                    \
-        hipError_t e_ = (expr);                             \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
-    } while (0)
 
 bool valid_sample(const rsa_sample_t &s)
 {
@@ -203,7 +124,7 @@ int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, uint32_t lds)
 {
     int nb = 0;
     int threads = 64 * (kTileWaves[tile] + 1);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kPersistentKernels[tile][wide][sparse], threads,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel(tile, wide, sparse), threads,
                                                      lds) !=
             hipSuccess ||
         nb < 1)
@@ -259,7 +180,9 @@ hipGraphExec_t cached_graph(rsa_ctx *c, const std::string &key)
     return nullptr;
 }
 
-}  // namespace
+}  // namespace rsa
+
+using namespace rsa;
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -334,7 +257,7 @@ int rsa_create(rsa_ctx **out, int device, uint64_t hbm_budget_bytes, const rsa_a
     for (int t = 0; t < kNumWaveTiles; ++t) {
         for (int w = 0; w < 2; ++w) {
             for (int sp = 0; sp < 2; ++sp) {
-                if (hipFuncSetAttribute(kPersistentKernels[t][w][sp],
+                if (hipFuncSetAttribute(persistent_kernel(t, w, sp),
                                         hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)(c->lds_max - 64)) != hipSuccess) {
                     delete c;
@@ -513,7 +436,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     HIP_TRY(c, hipEventRecord(b->ev_start, stream));
     std::vector<KernelArgs> args;
     for (auto &g : b->groups) {
-        KernelArgs a;
+        KernelArgs a{};
         a.descs = d_desc + g.first;
         a.n = g.count;
         a.tile = (uint32_t)g.waves;
@@ -539,7 +462,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
             int threads = 64 * (kTileWaves[g.waves] + 1);
             for (uint32_t j = 0; j < g.count; ++j, ++idx) {
                 int si = (int)(idx % kPlainStreams);
-                KernelArgs a;
+                KernelArgs a{};
                 a.descs = d_desc + g.first + j;
                 a.n = 1;
                 a.tile = (uint32_t)g.waves;
@@ -549,7 +472,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
                 a.results = d_res;
                 a.prof = b->d_prof;
                 void *kargs[] = {&a};
-                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.waves][g.wide][g.sparse], dim3(1), dim3(threads), kargs,
+                HIP_TRY(c, hipLaunchKernel(persistent_kernel(g.waves, g.wide, g.sparse), dim3(1), dim3(threads), kargs,
                                            g.lds, c->plain[si]));
             }
         }
@@ -588,7 +511,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
                     hipKernelNodeParams kp;
                     std::memset(&kp, 0, sizeof(kp));
                     void *kargs[] = {&args[i]};
-                    kp.func = (void *)kPersistentKernels[g.waves][g.wide][g.sparse];
+                    kp.func = (void *)persistent_kernel(g.waves, g.wide, g.sparse);
                     kp.gridDim = dim3(g.grid);
                     kp.blockDim = dim3(64 * (kTileWaves[g.waves] + 1));
                     kp.sharedMemBytes = g.lds;
@@ -612,7 +535,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
             for (size_t i = 0; i < args.size(); ++i) {
                 const Group &g = b->groups[i];
                 void *kargs[] = {&args[i]};
-                HIP_TRY(c, hipLaunchKernel(kPersistentKernels[g.waves][g.wide][g.sparse], dim3(g.grid),
+                HIP_TRY(c, hipLaunchKernel(persistent_kernel(g.waves, g.wide, g.sparse), dim3(g.grid),
                                            dim3(64 * (kTileWaves[g.waves] + 1)), kargs, g.lds, stream));
             }
         }

@@ -49,7 +49,8 @@ struct DevDesc {
     uint32_t spec_rows;   // rows read ahead of each clear (power of two)
     uint32_t tile;        // schedule id reported in the result
     uint32_t sparse;      // clear mode: 0 dense, 1 sparse (summary bits)
-    uint32_t pad1[3];
+    uint32_t pad1;
+    uint64_t slab;        // the sample's own slab, or 0 = the workgroup's slab
     FastDiv fL;        // division by L
     FastDiv fk;        // division by k
     FastDiv fC;        // division by 2k+2 (contacts per k-mer)
@@ -65,42 +66,6 @@ struct DevResult {
     int32_t status, tile;
     uint64_t alg_bytes, wchg_words;
 };
-
-// Per-sample device state, one slab per resident workgroup:
-//   avail[0], avail[1]  availability bitmaps of H / V placements: bit x%64 of
-//                       word x/64 of row y is anchor (y, x); words are stored
-//                       in 128-byte tiles of 2^lg_tr rows x 2^(4-lg_tr) words
-//   map                 int32 site -> k-mer id (deposit number), -1 = empty,
-//                       in 128-byte tiles of 2^lg_mr rows x 2^(5-lg_mr) sites
-//   node                per k-mer union-find record {parent, dx, dy, meta}:
-//                       (dx, dy) = anchor minus the parent's anchor, unwrapped;
-//                       meta (roots only) = rank | wraps-in-x << 8 | -in-y << 9
-//   kmer                per k-mer anchor site index | orientation << 31
-//   sum[0], sum[1]      summary bits of the availability bitmaps, row-major:
-//                       bit w%64 of word w/64 of row y is set while word w
-//                       of row y may be non-zero (used by the sparse clear)
-struct SlabLayout {
-    size_t avail0, avail1, sum0, sum1, map, node, kmer, total;
-};
-
-__host__ __device__ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
-
-__host__ __device__ inline SlabLayout slab_layout(uint32_t L, uint32_t k)
-{
-    SlabLayout s;
-    size_t wp = padded_words(L), lp = padded_side(L);
-    size_t cap = (size_t)L * L / k + 1;
-    size_t off = 0;
-    s.avail0 = off; off = align256(off + lp * wp * 8);
-    s.avail1 = off; off = align256(off + lp * wp * 8);
-    s.sum0 = off;   off = align256(off + lp * summary_words(L) * 8);   // summary bits, see below
-    s.sum1 = off;   off = align256(off + lp * summary_words(L) * 8);
-    s.map = off;    off = align256(off + lp * lp * 4);
-    s.node = off;   off = align256(off + cap * 16);
-    s.kmer = off;   off = align256(off + cap * 4);
-    s.total = off;
-    return s;
-}
 
 // Fixed capacities of the per-workgroup LDS areas.
 constexpr uint32_t kRing = 512;    // placements in flight between the waves
@@ -145,6 +110,78 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t L)
     return s;
 }
 
+// Per-sample device state, one slab per resident workgroup (batched runs) or
+// per sample (time-sliced runs):
+//   avail[0], avail[1]  availability bitmaps of H / V placements: bit x%64 of
+//                       word x/64 of row y is anchor (y, x); words are stored
+//                       in 128-byte tiles of 2^lg_tr rows x 2^(4-lg_tr) words
+//   map                 int32 site -> k-mer id (deposit number), -1 = empty,
+//                       in 128-byte tiles of 2^lg_mr rows x 2^(5-lg_mr) sites
+//   node                per k-mer union-find record {parent, dx, dy, meta}:
+//                       (dx, dy) = anchor minus the parent's anchor, unwrapped;
+//                       meta (roots only) = rank | wraps-in-x << 8 | -in-y << 9
+//   kmer                per k-mer anchor site index | orientation << 31
+//   sum[0], sum[1]      summary bits of the availability bitmaps, row-major:
+//                       bit w%64 of word w/64 of row y is set while word w
+//                       of row y may be non-zero (used by the sparse clear)
+//   state               SampleState, then the LDS row counts of a sample
+//                       that yielded (time-sliced runs only)
+struct SlabLayout {
+    size_t avail0, avail1, sum0, sum1, map, node, kmer, state, total;
+};
+
+// Status values of a time-sliced run besides 0 and the negative errors:
+// the sample yielded with its state saved, or was not reached in this launch.
+constexpr int32_t kStatusYielded = 1;
+constexpr int32_t kStatusNotRun = 2;
+// Descriptor flag of a time-sliced launch, above the public flags: the
+// sample has no saved state yet.
+constexpr uint32_t kDescFresh = 1u << 8;
+
+// What a sample that yields before jamming keeps in its slab.  The bitmaps,
+// map and union-find stay where they are; this record and the LDS row counts
+// are all the workgroup holds besides them between two deposits.
+struct SampleState {
+    uint32_t phase;      // 0 not started, 1 yielded, 2 finished
+    uint32_t t;          // deposits made
+    uint32_t P;          // placement of deposit t, already selected
+    uint32_t lab_stop;   // labelling ended early (both wrap steps known)
+    int32_t nx, ny;      // first wrap steps so far (1-based) or -1
+    int32_t status;
+    uint32_t pad;
+    uint64_t occ, seqh, wchg;
+    uint64_t pad2;
+    DevResult result;    // the final record once phase == 2
+};
+constexpr size_t kStateBytes = 256;
+static_assert(sizeof(SampleState) <= kStateBytes, "state record");
+
+__host__ __device__ inline uint32_t lds_count_bytes(uint32_t L)
+{
+    LdsLayout l = lds_layout(L);
+    return l.ring - l.cnt0;
+}
+
+__host__ __device__ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+__host__ __device__ inline SlabLayout slab_layout(uint32_t L, uint32_t k)
+{
+    SlabLayout s;
+    size_t wp = padded_words(L), lp = padded_side(L);
+    size_t cap = (size_t)L * L / k + 1;
+    size_t off = 0;
+    s.avail0 = off; off = align256(off + lp * wp * 8);
+    s.avail1 = off; off = align256(off + lp * wp * 8);
+    s.sum0 = off;   off = align256(off + lp * summary_words(L) * 8);   // summary bits, see below
+    s.sum1 = off;   off = align256(off + lp * summary_words(L) * 8);
+    s.map = off;    off = align256(off + lp * lp * 4);
+    s.node = off;   off = align256(off + cap * 16);
+    s.kmer = off;   off = align256(off + cap * 4);
+    s.state = off;  off = align256(off + kStateBytes + lds_count_bytes(L));
+    s.total = off;
+    return s;
+}
+
 struct KernelArgs {
     const DevDesc *descs;
     uint32_t n;
@@ -154,6 +191,8 @@ struct KernelArgs {
     uint64_t slab_stride;
     DevResult *results;
     unsigned long long *prof;   // kProfSlots counters per sample, or null
+    uint64_t quantum;           // wall-clock ticks a workgroup runs before its
+                                // sample yields; 0 = every sample to jamming
 };
 
 // Optional per-sample phase counters (device wall-clock ticks unless noted).

@@ -29,9 +29,11 @@
 
 #include "rsa_device.h"
 
-namespace rsa {
+#ifndef RSA_TU_WAVES
+#error "define RSA_TU_WAVES: the wave-count index (0 .. kNumWaveTiles - 1) this unit instantiates"
+#endif
 
-constexpr uint32_t kUnroll = 4;   // independent bitmap words in flight per lane
+namespace rsa {
 
 // Internal failure codes reported in the result's status field.  They mean a
 // broken invariant (counts that disagree with the bitmaps, a cycle in the
@@ -162,10 +164,15 @@ struct Hdr {
     int32_t nx, ny;          // first wrap steps (1-based) or -1
     uint32_t nclusters, nonwrap;
     int32_t status;          // 0, or kErrSelect / kErrLabel
-    uint32_t pad[2];
+    uint32_t t0;             // first step of this run (0, or where it resumed)
+    uint32_t p0;             // placement of step t0 on resume; on yield, of
+                             // the step the run stopped before
     unsigned long long wchg;
     unsigned long long occ;
     unsigned long long seqh;
+    uint32_t resumed;        // state restored from the slab
+    uint32_t preempt;        // the selecting wave stopped at its deadline
+    uint32_t lab_stop;       // labelling ended early (both wrap steps known)
 };
 
 struct Ctx {
@@ -766,8 +773,11 @@ struct TileCap {
 // Selecting wave
 // ---------------------------------------------------------------------------
 
+// deadline: wall-clock tick at which the run yields (0 = run to jamming); it
+// is checked every 16 steps, at a step whose placement is selected but not
+// yet deposited, so the saved state resumes exactly there.
 template <int NSEL, int ROWW, bool SPARSE>
-__device__ __forceinline__ void selector(Ctx &c)
+__device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
 {
     constexpr int CAP = TileCap<NSEL>::value;
     // read-ahead window (words per lane); for rows wider than 64 words the
@@ -776,16 +786,18 @@ __device__ __forceinline__ void selector(Ctx &c)
     const uint32_t lane = lane_id();
     __builtin_amdgcn_s_setprio(2);   // latency-critical chain first on a shared SIMD
     const uint32_t L = c.L, k = c.k;
-    uint64_t occ = 0, seqh = 0;
+    const uint32_t t_begin = c.h->t0;
+    uint64_t occ = 0, seqh = c.h->seqh;
     uint32_t wchg = 0;
     const bool prof = c.prof != nullptr;
     uint64_t p_start = prof ? tick() : 0, p_ring = 0, p_sel = 0, p_clr = 0, p0 = 0, spec_hits = 0;
     uint64_t p_hook = 0, p_proc = 0;
-    uint64_t u_pre = philox_u64(lane, c.sample, c.k0, c.k1);   // draws for steps 0..63 (lane = step)
-    uint32_t t = 0;
-    uint32_t P = 0;
-    bool alive = true;
-    {   // first placement
+    // draws for the 64 steps of t_begin's block (lane = step within the block)
+    uint64_t u_pre = philox_u64((t_begin & ~63u) + lane, c.sample, c.k0, c.k1);
+    uint32_t t = t_begin;
+    uint32_t P = c.h->p0;
+    bool alive = true, yielded = false;
+    if (!c.h->resumed) {   // first placement
         uint32_t inc2, v2, R, rin;
         uint32_t A = scan_top(c, inc2, v2);
         uint32_t r = uniform(draw_rank(bcast64(u_pre, 0), A));
@@ -798,8 +810,13 @@ __device__ __forceinline__ void selector(Ctx &c)
         if (!alive && A > 0 && lane == 0) c.h->status = kErrSelect;
     }
     while (alive) {
-        // ---- step t: P is known.  A correct run never deposits more than
-        // L*L/k k-mers; stop before the k-mer records would overflow.
+        // ---- step t: P is known.
+        if (deadline && (t & 15) == 0 && t != t_begin && tick() >= deadline) {
+            yielded = true;
+            break;
+        }
+        // A correct run never deposits more than L*L/k k-mers; stop before
+        // the k-mer records would overflow.
         if (t + 1 >= c.ncap) {
             if (lane == 0) c.h->status = kErrSelect;
             break;
@@ -909,6 +926,10 @@ __device__ __forceinline__ void selector(Ctx &c)
         atomicAdd(&c.h->occ, (unsigned long long)occ);
         atomicAdd(&c.h->wchg, (unsigned long long)wsum);
         c.h->seqh = seqh;
+        if (yielded) {
+            c.h->p0 = P;
+            c.h->preempt = 1;
+        }
         lds_store(&c.h->sel_done, t + 1);
     }
 }
@@ -920,7 +941,7 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
     const uint32_t lane = lane_id();
     __builtin_amdgcn_s_setprio(2);
     uint32_t wchg = 0;
-    uint32_t g = 0;
+    uint32_t g = c.h->t0;   // clear requests are numbered by step
     for (;;) {
         uint32_t gen;
         bool stop = false;
@@ -1247,13 +1268,15 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track)
     const uint32_t L = c.L, k = c.k, nC = 2 * k + 2;
     const FastDiv fC = c.fC;
     LabelState ls;
-    ls.nx = -1;
-    ls.ny = -1;
-    uint32_t tl = 0;
+    ls.nx = c.h->nx;
+    ls.ny = c.h->ny;
+    uint32_t tl = c.h->t0;
     const bool prof = c.prof != nullptr;
     uint64_t p_start = prof ? tick() : 0, p0 = 0;
     uint64_t p_idle = 0, p_map = 0, p_gather = 0, p_batches = 0, p_edges = 0;
-    for (;;) {
+    // a run that resumes after labelling ended early has nothing to label
+    bool stopped = c.h->lab_stop != 0;
+    while (!stopped) {
         uint32_t sp;
         bool finished = false;
         if (prof) p0 = tick();
@@ -1374,7 +1397,10 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track)
                 }
             }
         }
-        if (stop) break;
+        if (stop) {
+            stopped = true;
+            break;
+        }
         if (prof) p0 = tick();
         write_back(c);
         if (prof) prof_add(c, kProfLabWriteBack, tick() - p0);
@@ -1391,6 +1417,7 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track)
     if (lane == 0) {
         c.h->nx = ls.nx;
         c.h->ny = ls.ny;
+        c.h->lab_stop = stopped ? 1u : 0u;
         lds_store(&c.h->lab_exit, 1u);
     }
 }
@@ -1460,22 +1487,67 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
     c.h_val = c.h_key + kHash;
 }
 
+// One sample on one workgroup.  deadline = 0 runs it from the empty lattice
+// to jamming (batched runs, slab owned by the workgroup).  Otherwise the
+// slab is the sample's own and holds a SampleState: a finished sample
+// re-emits its result, a yielded one restores its row counts and header and
+// continues, and the run yields again at the deadline, saving them back.
 template <int NSEL, int ROWW, bool SPARSE>
-__device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d, uint8_t *lds)
+__device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d, uint8_t *lds,
+                                           uint64_t deadline)
 {
     constexpr uint32_t NT = 64 * (NSEL + 1);
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid >> 6;
+    uint8_t *slab = d.slab ? (uint8_t *)d.slab : a.slabs + (size_t)blockIdx.x * a.slab_stride;
     Ctx c;
-    carve(c, d, a.slabs + (size_t)blockIdx.x * a.slab_stride, lds);
+    carve(c, d, slab, lds);
     c.prof = a.prof ? a.prof + (size_t)d.out * kProfSlots : nullptr;
     const uint64_t p_init = c.prof ? tick() : 0;
     const uint32_t L = c.L;
     const bool h_only = (c.flags & 1u) != 0;
     const bool track = (c.flags & 2u) != 0;
+    const bool sliced = deadline != 0;
+    SampleState *st = (SampleState *)(slab + slab_layout(d.L, d.k).state);
+    uint32_t *saved_cnt = (uint32_t *)((uint8_t *)st + kStateBytes);
+    const uint32_t phase = sliced ? st->phase : 0u;
+    if (phase == 2) {
+        if (tid == 0) a.results[d.out] = st->result;
+        __syncthreads();
+        return;
+    }
 
-    // ---- initial state (Sec. II.A): all sites empty, all placements free
-    {
+    if (phase == 1) {
+        // ---- resume: row counts and the header from the slab
+        const uint32_t nw = lds_count_bytes(L) / 4;
+        for (uint32_t i = tid; i < nw; i += NT) c.cnt0[i] = saved_cnt[i];
+        if (tid == 0) {
+            Hdr *h = c.h;
+            const uint32_t t0 = st->t;
+            h->sel_progress = t0;
+            h->sel_done = 0;
+            h->lab_progress = t0;
+            h->lab_exit = 0;
+            h->clr_gen = t0;
+            h->clr_done = t0 * (NSEL - 1);
+            h->cur_p = 0;
+            h->nslots = 0;
+            h->nx = st->nx;
+            h->ny = st->ny;
+            h->nclusters = 0;
+            h->nonwrap = 0;
+            h->status = st->status;
+            h->t0 = t0;
+            h->p0 = st->P;
+            h->wchg = st->wchg;
+            h->occ = st->occ;
+            h->seqh = st->seqh;
+            h->resumed = 1;
+            h->preempt = 0;
+            h->lab_stop = st->lab_stop;
+        }
+    } else {
+        // ---- initial state (Sec. II.A): all sites empty, all placements free
         // the padded map (a multiple of 32 x 32 sites) is all -1
         int4 *m4 = (int4 *)c.map;
         const size_t q4 = (size_t)c.lp * c.lp / 4;
@@ -1536,9 +1608,14 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             h->nclusters = 0;
             h->nonwrap = 0;
             h->status = 0;
+            h->t0 = 0;
+            h->p0 = 0;
             h->wchg = 0;
             h->occ = 0;
             h->seqh = 0;
+            h->resumed = 0;
+            h->preempt = 0;
+            h->lab_stop = 0;
         }
     }
     __syncthreads();
@@ -1546,12 +1623,48 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
 
     // ---- the two chains
     if (wave == 0)
-        selector<NSEL, ROWW, SPARSE>(c);
+        selector<NSEL, ROWW, SPARSE>(c, deadline);
     else if (wave < (uint32_t)NSEL)
         helper<NSEL, SPARSE>(c, wave);
     else
         labeler<(NSEL >= 7 ? 16 : 8)>(c, track);
     __syncthreads();
+
+    if (c.h->preempt && c.h->status == 0) {
+        // ---- yield: save what the next run needs
+        const uint32_t nw = lds_count_bytes(L) / 4;
+        for (uint32_t i = tid; i < nw; i += NT) saved_cnt[i] = c.cnt0[i];
+        if (tid == 0) {
+            const Hdr *h = c.h;
+            const uint32_t tdone = h->sel_done - 1;
+            st->phase = 1;
+            st->t = tdone;
+            st->P = h->p0;
+            st->lab_stop = h->lab_stop;
+            st->nx = h->nx;
+            st->ny = h->ny;
+            st->status = 0;
+            st->occ = h->occ;
+            st->seqh = h->seqh;
+            st->wchg = h->wchg;
+            DevResult r;
+            r.n_jam = tdone;   // progress so far
+            r.n_wrap_x = h->nx;
+            r.n_wrap_y = h->ny;
+            r.n_wrap_any = -1;
+            r.occ_hash = 0;
+            r.seq_hash = 0;
+            r.n_clusters_jam = -1;
+            r.n_nonwrapping_jam = -1;
+            r.status = kStatusYielded;
+            r.tile = (int32_t)d.tile;
+            r.alg_bytes = 0;
+            r.wchg_words = h->wchg;
+            a.results[d.out] = r;
+        }
+        __syncthreads();
+        return;
+    }
 
     // ---- cluster census at jamming (Appendix A)
     const uint32_t njam = c.h->sel_done - 1;
@@ -1588,6 +1701,10 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
         r.alg_bytes = 4 * Lw * Lw + 16 * Lw * c.wd +
                       (uint64_t)njam * (4 * kw + 4 * (2 * kw + 2) + 8 * c.wd + 16) + 16 * r.wchg_words;
         a.results[d.out] = r;
+        if (sliced) {
+            st->result = r;
+            st->phase = 2;
+        }
     }
     __syncthreads();
 }
@@ -1597,33 +1714,65 @@ __global__ __launch_bounds__(64 * (NSEL + 1)) void rsa_persistent(KernelArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t next;
+    __shared__ uint64_t deadline;
+    if (threadIdx.x == 0) deadline = a.quantum ? tick() + a.quantum : 0;
     for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(a.queue, 1u);
+        // a time-sliced launch takes no new sample once its quantum is spent
+        if (threadIdx.x == 0) next = (deadline && tick() >= deadline) ? a.n : atomicAdd(a.queue, 1u);
         __syncthreads();
         const uint32_t i = next;
         __syncthreads();
         if (i >= a.n) return;
         const DevDesc d = a.descs[i];
-        run_sample<NSEL, ROWW, SPARSE>(a, d, lds);
+        run_sample<NSEL, ROWW, SPARSE>(a, d, lds, deadline);
     }
 }
 
+#if RSA_TU_WAVES == 0
 __global__ void rsa_reset_queues(uint32_t *queues, uint32_t n)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) queues[i] = 0;
 }
 
+// Before a time-sliced launch: every result reads "not run" until a
+// workgroup reaches its sample, a sample listed for the first time starts
+// from the empty lattice, and the work-queue counters restart at 0.
+__global__ void rsa_prepare_launch(const DevDesc *descs, uint32_t n, DevResult *res, uint32_t *queues,
+                                   uint32_t nq)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nq) queues[i] = 0;
+    if (i >= n) return;
+    res[i].status = kStatusNotRun;
+    const DevDesc d = descs[i];
+    if (d.flags & kDescFresh) {
+        SampleState *st = (SampleState *)((uint8_t *)d.slab + slab_layout(d.L, d.k).state);
+        st->phase = 0;
+    }
+}
+#endif
+
 }  // namespace rsa
 
-// Host-visible launch table: [tile waves][row words per lane 1 or 8][dense, sparse].
+// Host-visible launch table of this translation unit:
+// [row words per lane 1 or 8][dense, sparse] for one wave count.  The library
+// compiles this file once per wave-count index (RSA_TU_WAVES = 0 ..
+// kNumWaveTiles - 1) so that the instantiations build in parallel.
+#define RSA_CAT2(a, b) a##b
+#define RSA_CAT(a, b) RSA_CAT2(a, b)
+#define RSA_TABLE RSA_CAT(kPersistentKernelsW, RSA_TU_WAVES)
 namespace rsa {
-#define RSA_K(W) {{(const void *)&rsa_persistent<kTileWaves[W], 1, false>,   \
-                   (const void *)&rsa_persistent<kTileWaves[W], 1, true>},   \
-                  {(const void *)&rsa_persistent<kTileWaves[W], 8, false>,   \
-                   (const void *)&rsa_persistent<kTileWaves[W], 8, true>}}
-extern const void *kPersistentKernels[kNumWaveTiles][2][2];
-const void *kPersistentKernels[kNumWaveTiles][2][2] = {RSA_K(0), RSA_K(1), RSA_K(2), RSA_K(3), RSA_K(4)};
-#undef RSA_K
+extern const void *RSA_TABLE[2][2];
+const void *RSA_TABLE[2][2] = {
+    {(const void *)&rsa_persistent<kTileWaves[RSA_TU_WAVES], 1, false>,
+     (const void *)&rsa_persistent<kTileWaves[RSA_TU_WAVES], 1, true>},
+    {(const void *)&rsa_persistent<kTileWaves[RSA_TU_WAVES], 8, false>,
+     (const void *)&rsa_persistent<kTileWaves[RSA_TU_WAVES], 8, true>}};
+#if RSA_TU_WAVES == 0
+extern const void *kResetKernel;
+extern const void *kPrepareKernel;
 const void *kResetKernel = (const void *)&rsa_reset_queues;
+const void *kPrepareKernel = (const void *)&rsa_prepare_launch;
+#endif
 }  // namespace rsa

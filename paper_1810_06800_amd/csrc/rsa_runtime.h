@@ -1,0 +1,124 @@
+// rsa_runtime.h -- internal host runtime shared by the batch entry points
+// (rsa_capi.hip) and the request server (rsa_server.hip).  Not part of the C
+// ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rsa.h"
+#include "rsa_device.h"
+
+namespace rsa {
+// launch tables of the kernel translation units, one per wave count
+extern const void *kPersistentKernelsW0[2][2];
+extern const void *kPersistentKernelsW1[2][2];
+extern const void *kPersistentKernelsW2[2][2];
+extern const void *kPersistentKernelsW3[2][2];
+extern const void *kPersistentKernelsW4[2][2];
+extern const void *kResetKernel;
+extern const void *kPrepareKernel;
+static_assert(kNumWaveTiles == 5, "one launch table per wave count");
+
+// persistent kernel of a schedule: (wave-count index, rows wider than 64
+// words, sparse clear)
+const void *persistent_kernel(int waves, int wide, int sparse);
+}  // namespace rsa
+
+static_assert(sizeof(rsa_result_t) == sizeof(rsa::DevResult), "result layout");
+static_assert(sizeof(rsa_result_t) == 80, "result size");
+static_assert(sizeof(rsa_sample_t) == 24, "sample size");
+
+namespace rsa {
+
+constexpr int kPlainStreams = 4;
+
+struct Group {
+    int waves;               // index into kTileWaves (the kernel instantiation)
+    int wide;                // rows of more than 64 words (L > 4096)
+    int sparse;              // clear mode
+    uint32_t first, count;   // range in the planned descriptor array
+    uint32_t grid;
+    uint32_t lds;
+    size_t stride;           // slab bytes per resident workgroup
+    size_t slab_off;         // offset of this group's slabs in the batch allocation
+};
+
+struct Block {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Batch {
+    uint64_t id = 0;
+    uint32_t n = 0;
+    Block mem;
+    DevDesc *h_desc = nullptr;      // pinned
+    rsa_result_t *h_res = nullptr;  // pinned
+    hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_done = nullptr;
+    std::vector<Group> groups;
+    int mode = RSA_MODE_BATCHED;
+    unsigned long long *d_prof = nullptr;   // inside mem, or null
+};
+
+struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace rsa
+
+struct rsa_ctx {
+    int device = 0;
+    int cus = 0;
+    size_t lds_max = 0;
+    uint64_t budget = 0;
+    uint64_t held = 0;   // bytes currently allocated (in use + pooled)
+    bool custom = false;
+    rsa_allocator_t alloc{};
+    bool poisoned = false;
+    std::string last_error;
+    uint64_t next_id = 1;
+    std::map<uint64_t, rsa::Batch *> batches;
+    std::vector<rsa::Block> pool;   // free device blocks
+    std::vector<rsa::GraphEntry> graphs;
+    int64_t opt_mode = RSA_MODE_BATCHED, opt_tile = -1, opt_graph = 1, opt_slots = 0, opt_prof = 0;
+    int clock_khz = 0;
+    hipStream_t plain[rsa::kPlainStreams] = {};
+    hipEvent_t fork = nullptr, join[rsa::kPlainStreams] = {};
+    int resident[rsa::kNumTiles][4] = {};   // cached occupancy per tile and LDS class
+};
+
+namespace rsa {
+
+// Records msg as the context's last error and returns code.
+int fail(rsa_ctx *c, int code, const std::string &msg);
+// Poisons the context after a HIP failure; returns RSA_EDEVICE.
+int hip_fail(rsa_ctx *c, hipError_t e, const char *what);
+bool valid_sample(const rsa_sample_t &s);
+// Schedule the autotune table (or the built-in heuristic) picks for a shape.
+int default_tile(uint32_t L, uint32_t k);
+// Device memory through the caller's allocator or hipMalloc, within the budget.
+bool take_block(rsa_ctx *c, size_t bytes, Block &out);
+void give_block(rsa_ctx *c, Block b);
+// Workgroups of a schedule's kernel resident on the whole device at once.
+int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, uint32_t lds);
+// Kernel-side descriptor of a sample; `out` is its index in the result array.
+DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile);
+
+}  // namespace rsa
+
+#define HIP_TRY(ctx, expr)                                     \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return rsa::hip_fail(ctx, e_, #expr); \
+    } while (0)
+

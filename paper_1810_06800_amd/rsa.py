@@ -31,7 +31,8 @@ MODE_BATCHED, MODE_PLAIN = 0, 1
 EXPORTS = ("rsa_create", "rsa_footprint_bytes", "rsa_run_batch", "rsa_results",
            "rsa_batch_elapsed_ms", "rsa_batch_profile", "rsa_destroy", "rsa_strerror", "rsa_last_error",
            "rsa_set_option", "rsa_get_option", "rsa_num_tiles", "rsa_tile_for_shape",
-           "rsa_tile_shape")
+           "rsa_tile_shape", "rsa_server_create", "rsa_server_submit", "rsa_server_step",
+           "rsa_server_completed", "rsa_server_results", "rsa_server_stats", "rsa_server_destroy")
 
 
 class Sample(ctypes.Structure):
@@ -52,6 +53,18 @@ RESULT_FIELDS = [name for name, _ in Result._fields_]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("quantum_us", ctypes.c_uint32),
+                ("max_resident", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "requests_submitted", "requests_completed", "samples_queued", "samples_resident",
+        "samples_completed", "deposits_completed", "arena_bytes", "arena_used", "arena_peak",
+        "launches")]
 
 
 class Allocator(ctypes.Structure):
@@ -107,6 +120,20 @@ def lib() -> ctypes.CDLL:
     ip = ctypes.POINTER(ctypes.c_int)
     L.rsa_tile_shape.argtypes = [i32, ip, ip, ip, ip]
     L.rsa_tile_shape.restype = i32
+    L.rsa_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), vp, ctypes.POINTER(vp)]
+    L.rsa_server_create.restype = i32
+    L.rsa_server_submit.argtypes = [vp, ctypes.POINTER(Sample), u32, ctypes.POINTER(u64)]
+    L.rsa_server_submit.restype = i32
+    L.rsa_server_step.argtypes = [vp, i32]
+    L.rsa_server_step.restype = i32
+    L.rsa_server_completed.argtypes = [vp, ctypes.POINTER(u64), u32]
+    L.rsa_server_completed.restype = i32
+    L.rsa_server_results.argtypes = [vp, u64, ctypes.POINTER(Result), u32]
+    L.rsa_server_results.restype = i32
+    L.rsa_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.rsa_server_stats.restype = i32
+    L.rsa_server_destroy.argtypes = [vp]
+    L.rsa_server_destroy.restype = None
     _lib = L
     return L
 
@@ -258,6 +285,103 @@ class Context:
     def close(self) -> None:
         if getattr(self, "_h", None):
             self._lib.rsa_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """An rsa_server on a Context: requests of (L, k, seed, sample[, flags])
+    descriptors are queued by ``submit``, admitted by footprint and run in
+    time-sliced launches by ``step``; ``completed`` and ``results`` collect
+    them."""
+
+    def __init__(self, ctx: Context, arena_bytes: int = 0, quantum_us: int = 0,
+                 max_resident: int = 0, stream=None):
+        self._lib = ctx._lib
+        self.ctx = ctx
+        if stream is None:
+            import torch
+
+            stream = torch.cuda.current_stream(ctx.device).cuda_stream
+        cfg = ServerConfig(arena_bytes, quantum_us, max_resident)
+        h = ctypes.c_void_p()
+        rc = self._lib.rsa_server_create(ctx._h, ctypes.byref(cfg), ctypes.c_void_p(stream), ctypes.byref(h))
+        if rc != RSA_OK:
+            raise RsaError(rc, ctx.last_error())
+        self._h = h
+        self._sizes = {}
+
+    def submit(self, descs) -> int:
+        arr, n = make_samples(descs)
+        rid = ctypes.c_uint64()
+        rc = self._lib.rsa_server_submit(self._h, arr, n, ctypes.byref(rid))
+        if rc != RSA_OK:
+            raise RsaError(rc, self.ctx.last_error())
+        self._sizes[rid.value] = n
+        return rid.value
+
+    def step(self, wait: bool = False) -> int:
+        rc = self._lib.rsa_server_step(self._h, 1 if wait else 0)
+        if rc < 0:
+            raise RsaError(rc, self.ctx.last_error())
+        return rc
+
+    def completed(self, cap: int = 4096) -> list[int]:
+        ids = (ctypes.c_uint64 * cap)()
+        n = self._lib.rsa_server_completed(self._h, ids, cap)
+        if n < 0:
+            raise RsaError(n, self.ctx.last_error())
+        return [ids[i] for i in range(n)]
+
+    def results(self, request_id: int):
+        """Results of a completed request (list of dicts), or None if it has
+        not completed yet."""
+        n = self._sizes[request_id]
+        out = (Result * n)()
+        rc = self._lib.rsa_server_results(self._h, request_id, out, n)
+        if rc == RSA_ENOTREADY:
+            return None
+        if rc != RSA_OK:
+            raise RsaError(rc, self.ctx.last_error())
+        del self._sizes[request_id]
+        return [{f: getattr(out[i], f) for f in RESULT_FIELDS} for i in range(n)]
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        rc = self._lib.rsa_server_stats(self._h, ctypes.byref(st))
+        if rc != RSA_OK:
+            raise RsaError(rc, self.ctx.last_error())
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def run(self, requests, max_steps: int = 1 << 20) -> list[list[dict]]:
+        """Submit every request at once and step until all have completed
+        (RuntimeError after max_steps rounds)."""
+        ids = [self.submit(r) for r in requests]
+        done = {}
+        for _ in range(max_steps):
+            if len(done) == len(ids):
+                break
+            self.step(wait=True)
+            for rid in self.completed():
+                done[rid] = self.results(rid)
+        else:
+            raise RuntimeError(f"{len(ids) - len(done)} requests unfinished after {max_steps} steps")
+        return [done[i] for i in ids]
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.rsa_server_destroy(self._h)
             self._h = None
 
     def __enter__(self):

@@ -38,14 +38,20 @@ def test_every_declared_symbol_is_exported(rsa):
 def test_footprint_matches_layout(rsa):
     # two bitmaps of L*ceil(L/64) words, int32 map, 20 B per k-mer record,
     # every area 256-byte aligned
-    # (rows and columns padded so that every 128-byte tile shape fits)
+    # (rows and columns padded so that every 128-byte tile shape fits),
+    # plus a 256-byte state record and room for the 2L uint16 row counts and
+    # their sums over 64 and 4096 rows (time-sliced runs)
     def expect(L, k):
         a = lambda v: (v + 255) // 256 * 256
+        r16 = lambda v: (v + 15) // 16 * 16
         wp = ((L + 63) // 64 + 15) // 16 * 16
         lp = (L + 31) // 32 * 32
         cap = L * L // k + 1
         summary = a(lp * ((wp + 63) // 64) * 8)
-        return a(lp * wp * 8) * 2 + summary * 2 + a(4 * lp * lp) + a(16 * cap) + a(4 * cap)
+        rows = 2 * L
+        counts = r16((rows + 1) // 2 * 4) + r16((rows + 63) // 64 * 4) + r16((rows + 4095) // 4096 * 4)
+        return (a(lp * wp * 8) * 2 + summary * 2 + a(4 * lp * lp) + a(16 * cap) + a(4 * cap)
+                + a(256 + counts))
 
     for L, k in [(1, 1), (5, 3), (64, 8), (1024, 64), (16384, 1024), (32768, 4096)]:
         assert rsa.footprint_bytes(L, k) == expect(L, k)
