@@ -14,6 +14,9 @@ The JSON line also carries
   cpu_baseline  the serial CPU oracle on a bounded sample of the same
                 workload on the host's cores (rank 0, N = 1 only)
   plain         the per-sample-launch form on a subset of the same workload
+  serving       open-loop replays of request traces through the request
+                server (continuous batching): p50/p99 latency, served
+                deposits/s, offered vs served load
 """
 from __future__ import annotations
 
@@ -84,6 +87,39 @@ def cpu_baseline(descs, gpu_results, budget_s: float):
             "wall_s": round(wall, 3), "parity": f"{exact}/{n} bit-exact"}
 
 
+def serving_run(ctx, trace, window_s: float, quantum_us: int, arena_frac: float, label: str):
+    """Replay a request trace through the request server for window_s seconds."""
+    import torch
+
+    from paper_1810_06800_amd import rsa, serving
+
+    budget = int(torch.cuda.get_device_properties(0).total_memory * 0.9)
+    srv = rsa.Server(ctx, arena_bytes=int(budget * arena_frac), quantum_us=quantum_us)
+    try:
+        out = serving.replay(srv, trace, window_s,
+                             log=lambda m: print(f"# {label}: {m}", file=sys.stderr, flush=True))
+    finally:
+        srv.close()
+    out["label"] = label
+    out["quantum_us"] = quantum_us
+    return out
+
+
+def serving_summary(ctx, window_s: float, quantum_us: int, sustainable_rate: float):
+    """The Poisson trace at 200 requests/s over L in 256..16384 (far beyond
+    what one GPU serves: open-loop latency is queueing and the longest
+    chains), then a lighter labelled trace (L <= 1024) at a rate the GPU
+    sustains, to show unsaturated latency."""
+    from paper_1810_06800_amd import workloads
+
+    runs = [serving_run(ctx, workloads.serving_trace(), window_s, quantum_us, 0.8,
+                        "trace: 200 req/s, L 256..16384, k 2..L/8, n 1..64"),
+            serving_run(ctx, workloads.serving_trace(rate_hz=sustainable_rate, l_max=1024), window_s,
+                        quantum_us, 0.8,
+                        f"sustainable: {sustainable_rate:g} req/s, L 256..1024, k 2..L/8, n 1..64")]
+    return runs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +129,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-sample launch form")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="CPU seconds of oracle work")
+    ap.add_argument("--serve-window", type=float, default=20.0,
+                    help="seconds per serving replay (0 = skip the serving runs)")
+    ap.add_argument("--serve-quantum-us", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="requests/s of the sustainable replay")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): samples are independent, "
@@ -170,6 +210,11 @@ def main():
         out["plain"] = {"value": sum(r["n_jam"] for r in pres) / pw, "unit": "deposits/s",
                         "samples": len(sub), "launches": len(sub), "streams": 4,
                         "identical_to_batched": f"{same}/{len(sub)}"}
+    if args.serve_window > 0:
+        try:
+            out["serving"] = serving_summary(ctx, args.serve_window, args.serve_quantum_us, args.serve_rate)
+        except Exception as e:  # reported, not hidden: the main metric stands on its own
+            out["serving"] = {"error": repr(e)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(descs, results, args.cpu_budget)
     else:

@@ -227,7 +227,8 @@ int rsa_tile_shape(int tile, int *waves, int *bitmap_tile_rows, int *map_tile_ro
  * resumes it exactly there.  Between launches the host retires finished
  * samples (their arena space is reused) and admits queued samples, oldest
  * request first, as arena space and resident slots free up, so new requests
- * join work already on the device.  Results are the same, bit for bit, as
+ * join work already on the device (a sample too large for the free space is
+ * passed over by up to 256 later ones that fit).  Results are the same, bit for bit, as
  * rsa_run_batch's for the same descriptors, whatever else runs beside them.
  *
  * Two launches are kept in flight on the server's streams (forked from and
@@ -251,6 +252,8 @@ typedef struct {
     uint64_t samples_resident;   /* admitted, not yet retired                         */
     uint64_t samples_completed;
     uint64_t deposits_completed; /* n_jam summed over completed samples               */
+    uint64_t deposits_in_progress; /* deposits made so far by resident samples that
+                                      have not finished (as of the last retired launch) */
     uint64_t arena_bytes, arena_used, arena_peak;
     uint64_t launches;
 } rsa_server_stats_t;

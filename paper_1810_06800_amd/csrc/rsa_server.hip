@@ -11,6 +11,8 @@
 // kernel's SampleState); the next launch lists it again and it resumes.
 // Samples reached least often come first in each list, so a long chain
 // cannot starve new requests and no request waits behind another's launch.
+// A queued sample too large for the free arena space is passed over by
+// later ones that fit.
 // Two launches stay in flight; the host retires the older one, frees the
 // slabs of samples that finished, admits more, and enqueues the next.
 #include <deque>
@@ -25,20 +27,22 @@ constexpr int kStreams = 4;          // group launches fork onto these
 constexpr int kDepth = 2;            // launches in flight
 constexpr uint32_t kDefaultQuantumUs = 2000;
 constexpr uint32_t kDefaultResident = 4096;
-constexpr uint32_t kQueueWords = 4 * kNumWaveTiles;   // one counter per kernel group
+constexpr uint32_t kQueueWords = 64;   // one counter per kernel group (at most 40 groups)
+constexpr size_t kLookahead = 256;     // queued samples scanned past one that does not fit
 
 struct Sample {
     uint64_t req = 0;
     uint32_t idx = 0;         // position in its request
     rsa_sample_t s{};
     int tile = 0;
-    int key = 0;              // kernel group: (waves * 2 + wide) * 2 + sparse
+    int key = 0;              // kernel group (group_key)
     uint64_t off = 0, bytes = 0;
     bool resident = false;    // holds arena space
     bool listed = false;      // appeared in a launch (its state record exists)
     bool done = false;        // final result seen
     uint64_t last_launch = 0; // sequence number of the last launch listing it
     uint32_t runs = 0;        // launches in which a workgroup reached it
+    uint64_t progress = 0;    // deposits made, as of the last retired launch
 };
 
 struct Request {
@@ -92,9 +96,13 @@ namespace {
 
 uint32_t lds_bytes(uint32_t L) { return lds_layout(L).total; }
 
+// Kernel group of a sample: (waves, rows wider than 64 words, sparse clear)
+// select the kernel; the last bit splits lattices up to L = 1024 from larger
+// ones, whose row counts take more LDS and so fewer workgroups per CU.
 int group_key(const rsa_sample_t &s, int tile)
 {
-    return (tile_waves(tile) * 2 + (s.L > 4096 ? 1 : 0)) * 2 + tile_sparse(tile);
+    const int kernel = (tile_waves(tile) * 2 + (s.L > 4096 ? 1 : 0)) * 2 + tile_sparse(tile);
+    return kernel * 2 + (s.L > 1024 ? 1 : 0);
 }
 
 // Record a finished launch: progress of every sample it reached, final
@@ -109,7 +117,15 @@ void retire(rsa_server *v, const Launch &l)
         const rsa_result_t &r = b.h_res[i];
         if (r.status == kStatusNotRun) continue;
         ++sm.runs;
-        if (r.status == kStatusYielded || sm.done) continue;
+        if (sm.done) continue;
+        if (r.status == kStatusYielded) {
+            const uint64_t p = r.n_jam > 0 ? (uint64_t)r.n_jam : 0;
+            v->st.deposits_in_progress += p - sm.progress;
+            sm.progress = p;
+            continue;
+        }
+        v->st.deposits_in_progress -= sm.progress;
+        sm.progress = 0;
         sm.done = true;
         Request &q = v->requests[sm.req];
         q.res[sm.idx] = r;
@@ -152,17 +168,23 @@ int retire_ready(rsa_server *v, bool block)
 }
 
 // Admit queued samples in submission order while a slot and arena space are
-// free (a sample that does not fit waits, and so does everything behind it).
+// free.  A sample that does not fit stays queued, and later samples that do
+// fit are admitted past it (looking at most kLookahead entries ahead).
 void admit(rsa_server *v)
 {
-    while (!v->queue.empty() && v->n_resident < v->max_resident) {
-        Sample &sm = v->samples[v->queue.front()];
+    size_t i = 0, skipped = 0;
+    while (i < v->queue.size() && v->n_resident < v->max_resident && skipped < kLookahead) {
+        Sample &sm = v->samples[v->queue[i]];
         uint64_t off = 0;
-        if (!v->arena.alloc(sm.bytes, off)) break;
+        if (!v->arena.alloc(sm.bytes, off)) {
+            ++i;
+            ++skipped;
+            continue;
+        }
         sm.off = off;
         sm.resident = true;
         ++v->n_resident;
-        v->queue.pop_front();
+        v->queue.erase(v->queue.begin() + (std::ptrdiff_t)i);
     }
     v->st.arena_used = v->arena.used();
     v->st.arena_peak = v->arena.peak();
@@ -209,7 +231,7 @@ int launch(rsa_server *v)
     // samples up to what fits on the device, scaled down together when the
     // groups would not all be resident at once
     struct G {
-        int key;
+        int kern;   // (waves * 2 + wide) * 2 + sparse
         uint32_t first, count, lds, cap, grid;
     };
     std::vector<G> gs;
@@ -220,17 +242,23 @@ int launch(rsa_server *v)
             lds = std::max(lds, lds_bytes(v->samples[live[j]].s.L));
             ++j;
         }
-        const int waves = key >> 2, wide = (key >> 1) & 1, sparse = key & 1;
+        const int kern = key >> 1;
+        const int waves = kern >> 2, wide = (kern >> 1) & 1, sparse = kern & 1;
         uint32_t cap = (uint32_t)resident_blocks(c, waves, wide, sparse, lds);
-        gs.push_back(G{key, i, j - i, lds, cap, 0});
+        gs.push_back(G{kern, i, j - i, lds, cap, 0});
         i = j;
     }
-    double load = 0;
-    for (auto &g : gs) load += (double)std::min(g.count, g.cap) / g.cap;
-    for (auto &g : gs) {
-        uint32_t want = std::min(g.count, g.cap);
-        if (load > 1.0) want = (uint32_t)((double)want / load);
-        g.grid = std::max<uint32_t>(1, want);
+    // group g runs on stream g % kStreams: groups gi .. gi + kStreams - 1 run
+    // side by side and share the device
+    for (size_t r0 = 0; r0 < gs.size(); r0 += kStreams) {
+        const size_t r1 = std::min(gs.size(), r0 + kStreams);
+        double load = 0;
+        for (size_t gi = r0; gi < r1; ++gi) load += (double)std::min(gs[gi].count, gs[gi].cap) / gs[gi].cap;
+        for (size_t gi = r0; gi < r1; ++gi) {
+            uint32_t want = std::min(gs[gi].count, gs[gi].cap);
+            if (load > 1.0) want = (uint32_t)((double)want / load);
+            gs[gi].grid = std::max<uint32_t>(1, want);
+        }
     }
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipMemcpyAsync(b.d_desc, b.h_desc, (size_t)n * sizeof(DevDesc), hipMemcpyHostToDevice,
@@ -245,7 +273,7 @@ int launch(rsa_server *v)
     for (int s = 0; s < kStreams; ++s) HIP_TRY(c, hipStreamWaitEvent(v->streams[s], v->fork, 0));
     for (size_t gi = 0; gi < gs.size(); ++gi) {
         const G &g = gs[gi];
-        const int waves = g.key >> 2, wide = (g.key >> 1) & 1, sparse = g.key & 1;
+        const int waves = g.kern >> 2, wide = (g.kern >> 1) & 1, sparse = g.kern & 1;
         KernelArgs a{};
         a.descs = b.d_desc + g.first;
         a.n = g.count;

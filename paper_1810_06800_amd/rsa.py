@@ -63,8 +63,8 @@ class ServerConfig(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in (
         "requests_submitted", "requests_completed", "samples_queued", "samples_resident",
-        "samples_completed", "deposits_completed", "arena_bytes", "arena_used", "arena_peak",
-        "launches")]
+        "samples_completed", "deposits_completed", "deposits_in_progress", "arena_bytes",
+        "arena_used", "arena_peak", "launches")]
 
 
 class Allocator(ctypes.Structure):

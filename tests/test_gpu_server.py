@@ -74,6 +74,10 @@ def test_time_sliced_runs_are_exact(ctx, orc):
     _log("server: 8 requests, quantum 20 us")
     with rsa.Server(ctx, arena_bytes=1 << 30, quantum_us=20) as srv:
         got = srv.run(MIX)
+        # a finished sample's slab is freed once the last launch listing it
+        # (at most one launch behind) has been retired
+        for _ in range(4):
+            srv.step(wait=True)
         st = srv.stats()
     _log(f"server stats: {st}")
     flat = [d for r in MIX for d in r]
