@@ -21,7 +21,6 @@ The JSON line also carries
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -32,15 +31,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1810_06800_amd/csrc/rsa_kernels.hip", "paper_1810_06800_amd/csrc/rsa_device.h"]
-
-
-def kernel_digest() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str):
@@ -51,6 +41,8 @@ def measured_traffic(workload: str):
         return None
     with open(path) as f:
         t = json.load(f)
+    from paper_1810_06800_amd.profiling import kernel_digest
+
     if t.get("kernel_digest") != kernel_digest():
         return None
     return t.get("bytes_per_launch")
