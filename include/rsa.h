@@ -184,8 +184,9 @@ const char *rsa_last_error(rsa_ctx *ctx);
  *                  first; RSA_MODE_PLAIN: one launch per sample with a fixed
  *                  schedule, round-robin over four streams forked from and
  *                  joined back to the caller's stream (the comparison form)
- *   RSA_OPT_TILE   -1 (default) = schedule from the autotune table, else a
- *                  fixed schedule id in [0, RSA_NUM_TILES)
+ *   RSA_OPT_TILE   -1 (default) = schedule from the autotune table (see
+ *                  rsa_set_tile_table), else a fixed schedule id in
+ *                  [0, rsa_num_tiles())
  *   RSA_OPT_GRAPH  1 (default) = batched launches are captured into a
  *                  hipGraph once per shape signature and replayed; 0 = direct
  *   RSA_OPT_SLOTS  0 (default) = as many resident workgroups as fit, else
@@ -207,12 +208,23 @@ int rsa_get_option(rsa_ctx *ctx, int option, int64_t *value);
  * every word of the blocked rectangles is read; 1 sparse: per-word summary
  * bits are read first and only words that are still non-zero are touched).
  * Results never depend on the tile.  rsa_num_tiles: how many exist;
- * rsa_tile_for_shape: the one the autotune table picks for (L, k)
- * (RSA_EINVAL for an invalid shape); rsa_tile_shape: decode a tile id
- * (RSA_EINVAL if out of range; NULL outputs are skipped). */
+ * rsa_tile_for_shape: the built-in heuristic's tile for (L, k) (RSA_EINVAL
+ * for an invalid shape); rsa_tile_shape: decode a tile id (RSA_EINVAL if out
+ * of range; NULL outputs are skipped). */
 int rsa_num_tiles(void);
 int rsa_tile_for_shape(uint32_t L, uint32_t k);
 int rsa_tile_shape(int tile, int *waves, int *bitmap_tile_rows, int *map_tile_rows, int *sparse);
+
+/* Autotune table of a context: entry i says that samples of shape
+ * (L[i], k[i]) run with schedule tile[i] (measured fastest by the project's
+ * autotuner; the arrays are copied).  It replaces the previous table; n = 0
+ * clears it.  Shapes not in the table use the built-in heuristic, and
+ * RSA_OPT_TILE >= 0 overrides both.  RSA_EINVAL (table unchanged) for an
+ * invalid shape or tile id.  rsa_tile_for_sample: the tile a sample of
+ * (L, k) gets on this context now. */
+int rsa_set_tile_table(rsa_ctx *ctx, const uint32_t *L, const uint32_t *k, const int32_t *tile,
+                       uint32_t n);
+int rsa_tile_for_sample(rsa_ctx *ctx, uint32_t L, uint32_t k);
 
 /* ---------------------------------------------------------------------------
  * Request server: continuous batching of independent runs (Sec. II.A: every

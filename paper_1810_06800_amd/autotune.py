@@ -1,0 +1,139 @@
+"""Autotuner of the per-shape schedule ("tile") of the persistent kernels.
+
+A tile fixes the selecting waves per sample, the bitmap tile height, the
+site-map tile height and the clear mode (include/rsa.h).  Results never
+depend on it, so the tuner is free to pick the fastest: for each (L, k) it
+times batches of that shape on the GPU (HIP events around the kernels,
+best of ``reps``) under a forced tile, walking one coordinate at a time from
+the built-in heuristic's tile (waves, clear mode, bitmap tile, map tile), and
+keeps the fastest.  Every tile's results are compared with the first tile's,
+field by field, and a difference aborts the run.
+
+    python -m paper_1810_06800_amd.autotune [--out paper_1810_06800_amd/tiles.json]
+
+writes the table that rsa.Context hands to the library (rsa_set_tile_table)
+together with every measurement.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+from . import rsa
+
+# (L, k, samples, reps): the benchmark shapes, with enough samples per batch
+# to load the device the way the benchmark does
+SHAPES = [
+    (64, 8, 256, 3),
+    (256, 4, 256, 3),
+    (512, 32, 256, 3),
+    (1024, 64, 512, 2),
+    (2048, 128, 128, 2),
+    (4096, 256, 96, 2),
+    (16384, 1024, 16, 1),
+    (32768, 4096, 8, 1),
+]
+WAVES = (0, 1, 2, 3)          # wave-count indices tried (1, 2, 3, 7 selecting waves)
+LG_TR = (0, 1, 2, 3, 4)
+LG_MR = (0, 1, 2, 3, 4, 5)
+FIELDS = ("n_jam", "n_wrap_x", "n_wrap_y", "n_wrap_any", "occ_hash", "seq_hash", "alg_bytes",
+          "wchg_words", "status")
+
+
+def decode(tile: int):
+    """(wave index, lg_tr, lg_mr, sparse) of a tile id."""
+    nw = 5
+    return tile % nw, (tile // nw) % 5, (tile // (nw * 5)) % 6, tile // (nw * 5 * 6)
+
+
+def encode(waves: int, lg_tr: int, lg_mr: int, sparse: int) -> int:
+    return waves + 5 * (lg_tr + 5 * (lg_mr + 6 * sparse))
+
+
+def time_tile(ctx, descs, tile: int, reps: int):
+    ctx.set_option(rsa.OPT_TILE, tile)
+    best, res = None, None
+    for _ in range(reps):
+        b = ctx.run_batch(descs)
+        ms = ctx.elapsed_ms(b)
+        res = ctx.results(b)
+        best = ms if best is None else min(best, ms)
+    return best, res
+
+
+def tune_shape(ctx, L: int, k: int, n: int, reps: int, log=print):
+    descs = [(L, k, 1000 + L + k, s, 0) for s in range(n)]
+    start = rsa.tile_for_shape(L, k)
+    tried = {}
+    ref = None
+
+    def measure(tile):
+        nonlocal ref
+        if tile in tried:
+            return tried[tile]
+        ms, res = time_tile(ctx, descs, tile, reps)
+        key = [tuple(r[f] for f in FIELDS) for r in res]
+        if ref is None:
+            ref = key
+        elif key != ref:
+            raise RuntimeError(f"tile {tile} changed the results of ({L}, {k})")
+        if any(r["status"] != 0 for r in res):
+            raise RuntimeError(f"tile {tile} failed on ({L}, {k})")
+        tried[tile] = ms
+        log(f"  ({L}, {k}) tile {tile} {decode(tile)}: {ms:.3f} ms")
+        return ms
+
+    best = start
+    best_ms = measure(start)
+    # one selecting wave per 64-word row block is hopeless for k >= 1024
+    waves = tuple(w for w in WAVES if k < 1024 or w >= 2)
+    for dim, values in ((0, waves), (3, (0, 1)), (1, LG_TR), (2, LG_MR)):
+        for v in values:
+            parts = list(decode(best))
+            parts[dim] = v
+            t = encode(*parts)
+            ms = measure(t)
+            if ms < best_ms:
+                best, best_ms = t, ms
+    return {"L": L, "k": k, "tile": best, "shape": decode(best), "ms": best_ms,
+            "heuristic_tile": start, "heuristic_ms": tried[start], "samples": n, "reps": reps,
+            "tried": {str(t): round(ms, 4) for t, ms in sorted(tried.items())}}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_1810_06800_amd.autotune")
+    ap.add_argument("--out", default=rsa.TILE_TABLE)
+    ap.add_argument("--shapes", default="", help="comma list of LxK to tune (default: all)")
+    a = ap.parse_args(argv)
+    import torch
+
+    shapes = SHAPES
+    if a.shapes:
+        want = {tuple(int(v) for v in s.split("x")) for s in a.shapes.split(",")}
+        shapes = [s for s in SHAPES if (s[0], s[1]) in want]
+    ctx = rsa.Context(0, tile_table=None)
+    entries = []
+    t0 = time.time()
+    for L, k, n, reps in shapes:
+        print(f"# tuning ({L}, {k}) on {n} samples", flush=True)
+        e = tune_shape(ctx, L, k, n, reps, log=lambda m: print(m, flush=True))
+        print(f"# ({L}, {k}): tile {e['tile']} {e['ms']:.3f} ms (heuristic {e['heuristic_tile']} "
+              f"{e['heuristic_ms']:.3f} ms)", flush=True)
+        entries.append(e)
+    ctx.set_option(rsa.OPT_TILE, -1)
+    ctx.close()
+    out = {"device": torch.cuda.get_device_name(0), "seconds": round(time.time() - t0, 1),
+           "method": "coordinate walk from the heuristic tile: waves, clear mode, bitmap tile rows, "
+                     "map tile rows; best of reps HIP-event kernel times per tile; results identical "
+                     "across all tiles",
+           "entries": entries}
+    with open(a.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"# wrote {a.out}", flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

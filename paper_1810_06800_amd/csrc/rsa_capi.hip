@@ -50,6 +50,13 @@ int default_tile(uint32_t L, uint32_t k)
     return make_tile(waves, 3, 3, k >= 512 ? 1 : 0);
 }
 
+int sample_tile(const rsa_ctx *c, uint32_t L, uint32_t k)
+{
+    if (c->opt_tile >= 0) return (int)c->opt_tile;
+    auto it = c->tile_table.find({L, k});
+    return it != c->tile_table.end() ? it->second : default_tile(L, k);
+}
+
 // Relative cost of a sample: deposits (about 0.7 L^2 / k) times the words a
 // deposit clears spread over the tile's waves, plus a per-step latency floor.
 double sample_cost(uint32_t L, uint32_t k, int tile)
@@ -220,6 +227,25 @@ int rsa_tile_for_shape(uint32_t L, uint32_t k)
     return default_tile(L, k);
 }
 
+int rsa_set_tile_table(rsa_ctx *c, const uint32_t *L, const uint32_t *k, const int32_t *tile, uint32_t n)
+{
+    if (!c || (n > 0 && (!L || !k || !tile))) return RSA_EINVAL;
+    std::map<std::pair<uint32_t, uint32_t>, int> t;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (k[i] < 1 || k[i] > L[i] || L[i] > 32768 || tile[i] < 0 || tile[i] >= kNumTiles)
+            return fail(c, RSA_EINVAL, "bad tile table entry " + std::to_string(i));
+        t[{L[i], k[i]}] = tile[i];
+    }
+    c->tile_table.swap(t);
+    return RSA_OK;
+}
+
+int rsa_tile_for_sample(rsa_ctx *c, uint32_t L, uint32_t k)
+{
+    if (!c || k < 1 || k > L || L > 32768) return RSA_EINVAL;
+    return sample_tile(c, L, k);
+}
+
 int rsa_tile_shape(int tile, int *waves, int *bitmap_tile_rows, int *map_tile_rows, int *sparse)
 {
     if (tile < 0 || tile >= kNumTiles) return RSA_EINVAL;
@@ -340,7 +366,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     // group key: (wave count, rows wider than 64 words, clear mode) -> kernel
     std::vector<int> tiles(n), keys(n);
     for (uint32_t i = 0; i < n; ++i) {
-        tiles[i] = c->opt_tile >= 0 ? (int)c->opt_tile : default_tile(s[i].L, s[i].k);
+        tiles[i] = sample_tile(c, s[i].L, s[i].k);
         keys[i] = (tile_waves(tiles[i]) * 2 + (s[i].L > 4096 ? 1 : 0)) * 2 + tile_sparse(tiles[i]);
     }
     std::vector<uint32_t> order(n);

@@ -95,6 +95,7 @@ struct rsa_ctx {
     hipStream_t plain[rsa::kPlainStreams] = {};
     hipEvent_t fork = nullptr, join[rsa::kPlainStreams] = {};
     int resident[rsa::kNumTiles][4] = {};   // cached occupancy per tile and LDS class
+    std::map<std::pair<uint32_t, uint32_t>, int> tile_table;   // (L, k) -> measured best tile
 };
 
 namespace rsa {
@@ -104,8 +105,11 @@ int fail(rsa_ctx *c, int code, const std::string &msg);
 // Poisons the context after a HIP failure; returns RSA_EDEVICE.
 int hip_fail(rsa_ctx *c, hipError_t e, const char *what);
 bool valid_sample(const rsa_sample_t &s);
-// Schedule the autotune table (or the built-in heuristic) picks for a shape.
+// Built-in schedule heuristic for a shape.
 int default_tile(uint32_t L, uint32_t k);
+// Schedule of a sample: the forced tile option, else the context's autotune
+// table entry for (L, k), else the heuristic.
+int sample_tile(const rsa_ctx *c, uint32_t L, uint32_t k);
 // Device memory through the caller's allocator or hipMalloc, within the budget.
 bool take_block(rsa_ctx *c, size_t bytes, Block &out);
 void give_block(rsa_ctx *c, Block b);

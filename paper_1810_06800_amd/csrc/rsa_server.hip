@@ -403,7 +403,7 @@ int rsa_server_submit(rsa_server *v, const rsa_sample_t *s, uint32_t n, uint64_t
         sm.req = id;
         sm.idx = i;
         sm.s = s[i];
-        sm.tile = c->opt_tile >= 0 ? (int)c->opt_tile : default_tile(s[i].L, s[i].k);
+        sm.tile = sample_tile(c, s[i].L, s[i].k);
         sm.key = group_key(s[i], sm.tile);
         sm.bytes = slab_layout(s[i].L, s[i].k).total;
         v->queue.push_back(h);

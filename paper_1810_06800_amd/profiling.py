@@ -32,12 +32,15 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = ["paper_1810_06800_amd/csrc/rsa_kernels.hip", "paper_1810_06800_amd/csrc/rsa_device.h"]
+# the kernel sources and the autotune table (which picks the tile a workload runs with)
+KERNEL_SOURCES = ["paper_1810_06800_amd/csrc/rsa_kernels.hip", "paper_1810_06800_amd/csrc/rsa_device.h",
+                  "paper_1810_06800_amd/tiles.json"]
 PERSISTENT = "rsa_persistent"
 
 
 def kernel_digest() -> str:
-    """sha256 prefix of the kernel sources (counter readings are tied to it)."""
+    """sha256 prefix of the kernel sources and the tile table (counter
+    readings are tied to it)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:

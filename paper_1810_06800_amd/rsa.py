@@ -15,6 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librsa_hip.so")
+TILE_TABLE = os.path.join(HERE, "tiles.json")   # written by paper_1810_06800_amd.autotune
 
 RSA_OK, RSA_EINVAL, RSA_ENOMEM, RSA_EDEVICE, RSA_ENOTREADY, RSA_EBUSY, RSA_ENOTFOUND = (
     0, -1, -2, -3, -4, -5, -6)
@@ -31,7 +32,7 @@ MODE_BATCHED, MODE_PLAIN = 0, 1
 EXPORTS = ("rsa_create", "rsa_footprint_bytes", "rsa_run_batch", "rsa_results",
            "rsa_batch_elapsed_ms", "rsa_batch_profile", "rsa_destroy", "rsa_strerror", "rsa_last_error",
            "rsa_set_option", "rsa_get_option", "rsa_num_tiles", "rsa_tile_for_shape",
-           "rsa_tile_shape", "rsa_server_create", "rsa_server_submit", "rsa_server_step",
+           "rsa_tile_shape", "rsa_set_tile_table", "rsa_tile_for_sample", "rsa_server_create", "rsa_server_submit", "rsa_server_step",
            "rsa_server_completed", "rsa_server_results", "rsa_server_stats", "rsa_server_destroy")
 
 
@@ -120,6 +121,11 @@ def lib() -> ctypes.CDLL:
     ip = ctypes.POINTER(ctypes.c_int)
     L.rsa_tile_shape.argtypes = [i32, ip, ip, ip, ip]
     L.rsa_tile_shape.restype = i32
+    L.rsa_set_tile_table.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                     ctypes.POINTER(ctypes.c_int32), u32]
+    L.rsa_set_tile_table.restype = i32
+    L.rsa_tile_for_sample.argtypes = [vp, u32, u32]
+    L.rsa_tile_for_sample.restype = i32
     L.rsa_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), vp, ctypes.POINTER(vp)]
     L.rsa_server_create.restype = i32
     L.rsa_server_submit.argtypes = [vp, ctypes.POINTER(Sample), u32, ctypes.POINTER(u64)]
@@ -191,12 +197,26 @@ def _torch_allocator(device: int):
     return Allocator(fa, ff, None), (fa, ff)
 
 
+def load_tile_table(path: str = TILE_TABLE):
+    """[(L, k, tile)] from an autotune table file ([] if it does not exist)."""
+    import json
+
+    if not path or not os.path.exists(path):
+        return []
+    with open(path) as f:
+        t = json.load(f)
+    return [(int(e["L"]), int(e["k"]), int(e["tile"])) for e in t["entries"]]
+
+
 class Context:
     """An rsa_ctx on one device.  ``allocator='torch'`` (default) takes device
     memory from torch's caching allocator; ``'hip'`` lets the library call
-    hipMalloc.  Work goes to torch's current stream unless a stream is given."""
+    hipMalloc.  Work goes to torch's current stream unless a stream is given.
+    ``tile_table`` is the autotune table file handed to the library (the
+    package's tiles.json by default; None for the built-in heuristic only)."""
 
-    def __init__(self, device: int = 0, budget_bytes: int = 0, allocator: str = "torch"):
+    def __init__(self, device: int = 0, budget_bytes: int = 0, allocator: str = "torch",
+                 tile_table: str | None = TILE_TABLE):
         self._lib = lib()
         self.device = device
         self._keep = None
@@ -215,6 +235,23 @@ class Context:
         if rc != RSA_OK:
             raise RsaError(rc, "rsa_create")
         self._h = handle
+        self.set_tile_table(load_tile_table(tile_table) if tile_table else [])
+
+    def set_tile_table(self, entries) -> None:
+        """Hand the library an autotune table: [(L, k, tile)]."""
+        n = len(entries)
+        Ls = (ctypes.c_uint32 * max(n, 1))(*[e[0] for e in entries])
+        ks = (ctypes.c_uint32 * max(n, 1))(*[e[1] for e in entries])
+        ts = (ctypes.c_int32 * max(n, 1))(*[e[2] for e in entries])
+        rc = self._lib.rsa_set_tile_table(self._h, Ls, ks, ts, n)
+        if rc != RSA_OK:
+            raise RsaError(rc, self.last_error())
+
+    def tile_for_sample(self, L: int, k: int) -> int:
+        rc = self._lib.rsa_tile_for_sample(self._h, L, k)
+        if rc < 0:
+            raise RsaError(rc, self.last_error())
+        return rc
 
     # -- options
     def set_option(self, option: int, value: int) -> None:

@@ -93,3 +93,23 @@ def test_workloads_shapes():
     assert all(2 <= r["k"] <= r["L"] // 8 and 1 <= r["n"] <= 64 for r in tr)
     gaps = [b["arrival_s"] - a["arrival_s"] for a, b in zip(tr, tr[1:])]
     assert 0.003 < sum(gaps) / len(gaps) < 0.008
+
+
+def test_autotune_table_is_well_formed(rsa):
+    """The committed autotune table names valid shapes and tiles, each the
+    fastest of the tiles it records for its shape."""
+    import json
+
+    with open(rsa.TILE_TABLE) as f:
+        t = json.load(f)
+    assert t["entries"]
+    n = rsa.num_tiles()
+    for e in t["entries"]:
+        assert 1 <= e["k"] <= e["L"] <= 32768
+        assert 0 <= e["tile"] < n
+        tried = {int(k): v for k, v in e["tried"].items()}
+        assert e["tile"] in tried and e["heuristic_tile"] in tried
+        assert tried[e["tile"]] == min(tried.values())
+        assert rsa.tile_shape(e["tile"])[0] in (1, 2, 3, 7)
+    assert [(L, k, tile) for L, k, tile in rsa.load_tile_table()] == [
+        (e["L"], e["k"], e["tile"]) for e in t["entries"]]

@@ -175,6 +175,49 @@ def test_mixed_batch_workload(ctx, orc):
     check(sub, [got[i] for i in pick], orc.run_many(sub, threads=min(16, os.cpu_count() or 1)))
 
 
+def test_large_workloads_sampled(ctx):
+    """L = 16384, k = 1024 (32 samples) and L = 32768, k = 4096 (8 samples) at
+    full size, each as one batch as the benchmark launches it; three samples
+    of each against the oracle's stored results (tests/golden/
+    make_large_expected.py), and the proven bounds on every sample."""
+    import json
+
+    from paper_1810_06800_amd import workloads
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "large_expected.json")) as f:
+        golden = json.load(f)
+    want = {tuple(d): r for d, r in zip(golden["descs"], golden["results"])}
+    for name in ("large_16k", "large_32k"):
+        descs = workloads.CONFIGS[name]()
+        _log(f"{name}: {len(descs)} samples")
+        got = ctx.run(descs)
+        for d, g in zip(descs, got):
+            L, k = d[0], d[1]
+            assert g["status"] == 0, (d, g["status"])
+            assert 1 <= g["n_wrap_any"] <= g["n_jam"] and g["n_jam"] * k <= L * L
+        picked = [(d, g) for d, g in zip(descs, got) if tuple(d) in want]
+        assert len(picked) == 3
+        check([d for d, _ in picked], [g for _, g in picked], [want[tuple(d)] for d, _ in picked])
+
+
+def test_autotune_table_applied(ctx, orc):
+    """Shapes in the autotune table run with the table's tile, others with the
+    heuristic, and results match the oracle either way."""
+    from paper_1810_06800_amd import rsa
+
+    table = {(L, k): t for L, k, t in rsa.load_tile_table()}
+    assert table
+    descs = [(2048, 128, 5, 0, 0), (512, 32, 5, 1, 0), (300, 7, 5, 2, 0)]
+    got = ctx.run(descs)
+    for d, g in zip(descs, got):
+        want_tile = table.get(d[:2], rsa.tile_for_shape(d[0], d[1]))
+        assert g["tile"] == want_tile == ctx.tile_for_sample(d[0], d[1])
+    check(descs, got, orc.run_many(descs))
+    with pytest.raises(rsa.RsaError):
+        ctx.set_tile_table([(4, 8, 0)])
+    assert ctx.tile_for_sample(2048, 128) == table[(2048, 128)]   # table unchanged
+
+
 def test_invalid_descriptors_rejected(ctx):
     from paper_1810_06800_amd import rsa
 
