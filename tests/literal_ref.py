@@ -108,9 +108,42 @@ def clusters_and_windings(occ: np.ndarray):
     return label, out
 
 
-def run(L: int, k: int, seed: int, sample: int, h_only: bool = False) -> dict:
+def contacts(owner: np.ndarray, orient: list[int]) -> tuple[int, int, int]:
+    """(n_x, n_y, n_xy) of a configuration (Eq. 12): for every site, its right
+    and its lower neighbour; a pair of occupied sites in different k-mers
+    counts for both-horizontal, both-vertical or perpendicular."""
+    L = owner.shape[0]
+    out = [0, 0, 0]
+    for y in range(L):
+        for x in range(L):
+            a = owner[y, x]
+            if a < 0:
+                continue
+            for ny, nx in ((y, (x + 1) % L), ((y + 1) % L, x)):
+                b = owner[ny, nx]
+                if b < 0 or b == a:
+                    continue
+                oa, ob = orient[a], orient[b]
+                out[2 if oa != ob else oa] += 1
+    return tuple(out)
+
+
+def size_histogram(occ: np.ndarray) -> dict[int, int]:
+    """{cluster size in sites: number of clusters} of a configuration."""
+    hist = {}
+    for size, _, _ in clusters_and_windings(occ)[1]:
+        hist[size] = hist.get(size, 0) + 1
+    return hist
+
+
+def run(L: int, k: int, seed: int, sample: int, h_only: bool = False, snap_step: int = 0) -> dict:
+    """One run to jamming.  Besides the result fields: ``owner`` (final site ->
+    deposit number grid), ``orient`` (per deposit, 0 = H, 1 = V) and, for
+    snap_step > 0, ``snap_hist`` (cluster sizes right after that deposit)."""
     occ = np.zeros((L, L), dtype=bool)
     owner = -np.ones((L, L), dtype=np.int64)
+    orient = []
+    snap_hist = None
     seq = []
     n_x = n_y = -1
     seq_hash = 0
@@ -132,7 +165,10 @@ def run(L: int, k: int, seed: int, sample: int, h_only: bool = False) -> dict:
             assert not occ[sy, sx]
             occ[sy, sx] = True
             owner[sy, sx] = t
+        orient.append(o)
         _, cl = clusters_and_windings(occ)
+        if snap_step and t + 1 == snap_step:
+            snap_hist = size_histogram(occ)
         if n_x < 0 and any(c[1] for c in cl):
             n_x = t + 1
         if n_y < 0 and any(c[2] for c in cl):
@@ -153,4 +189,7 @@ def run(L: int, k: int, seed: int, sample: int, h_only: bool = False) -> dict:
         "seq": seq,
         "n_clusters_jam": len(cl),
         "n_nonwrapping_jam": sum(1 for c in cl if not (c[1] or c[2])),
+        "owner": owner,
+        "orient": orient,
+        "snap_hist": snap_hist,
     }
