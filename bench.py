@@ -50,10 +50,12 @@ def measured_traffic(workload: str):
 
 def describe(workload: str, descs) -> str:
     shapes = sorted({(d[0], d[1]) for d in descs})
+    flags = sorted({d[4] for d in descs})
+    extra = f", flags {flags}" if flags != [0] else ""
     if len(shapes) == 1:
         L, k = shapes[0]
-        return f"RSA k-mers to jamming, L={L} k={k}, {len(descs)} samples"
-    return f"RSA k-mers to jamming, {len(descs)} samples over (L,k) in {shapes}"
+        return f"RSA k-mers to jamming, L={L} k={k}, {len(descs)} samples{extra}"
+    return f"RSA k-mers to jamming, {len(descs)} samples over (L,k) in {shapes}{extra}"
 
 
 def cpu_baseline(descs, gpu_results, budget_s: float):
@@ -121,6 +123,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-sample launch form")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="CPU seconds of oracle work")
+    ap.add_argument("--flags", type=int, default=0,
+                    help="rsa_flags ORed into every descriptor (4 = contact census at jamming)")
     ap.add_argument("--serve-window", type=float, default=20.0,
                     help="seconds per serving replay (0 = skip the serving runs)")
     ap.add_argument("--serve-quantum-us", type=int, default=2000)
@@ -140,6 +144,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     descs = workloads.CONFIGS[args.workload]()
+    if args.flags:
+        descs = [tuple(d[:4]) + (d[4] | args.flags,) for d in descs]
     ctx = rsa.Context(0)
     stream = torch.cuda.current_stream()
 

@@ -61,7 +61,12 @@ enum rsa_flags {
     /* Also report the number of clusters and of non-wrapping clusters at
      * jamming (Appendix A: the latter is always 0).  Keeps cluster labelling
      * running to jamming instead of stopping once both wrap steps are known. */
-    RSA_FLAG_TRACK_CLUSTERS = 1u << 1
+    RSA_FLAG_TRACK_CLUSTERS = 1u << 1,
+    /* Also report the contact census of the jammed state (Eq. 12): pairs of
+     * nearest-neighbour sites in different k-mers, both horizontal, both
+     * vertical or perpendicular.  Keeps the site map written to jamming and
+     * adds one pass over it. */
+    RSA_FLAG_CONTACTS = 1u << 2
 };
 
 /* Opaque context.  Owns every device allocation made on its behalf. */
@@ -75,7 +80,7 @@ typedef struct {
     uint32_t sample, flags;
 } rsa_sample_t;
 
-/* Result of one run (80 bytes).  Counts are 1-based deposit numbers; -1 means
+/* Result of one run (104 bytes).  Counts are 1-based deposit numbers; -1 means
  * "never" (possible for one direction on small tori).
  *   n_jam        k-mers on the lattice at jamming
  *   n_wrap_x/_y  deposit after which some cluster first wraps in x / in y
@@ -95,6 +100,11 @@ typedef struct {
  *                4k (map) + 4(2k+2) (contacts) + 8*ceil(L/64) (select row)
  *                + 16 (k-mer record); 16 B per availability word changed
  *   wchg_words   availability words whose value changed, summed over steps
+ *   n_contacts_x, n_contacts_y, n_contacts_xy   contact census at jamming,
+ *                -1 unless RSA_FLAG_CONTACTS: over every site and its right
+ *                and lower neighbour (mod L), pairs of occupied sites in
+ *                different k-mers that are both horizontal / both vertical /
+ *                of different orientations; n*_xy = n_xy / (n_x + n_y + n_xy)
  */
 typedef struct {
     int64_t n_jam, n_wrap_x, n_wrap_y, n_wrap_any;
@@ -102,6 +112,7 @@ typedef struct {
     int32_t n_clusters_jam, n_nonwrapping_jam;
     int32_t status, tile;
     uint64_t alg_bytes, wchg_words;
+    int64_t n_contacts_x, n_contacts_y, n_contacts_xy;
 } rsa_result_t;
 
 /* Optional device allocator.  alloc returns device memory of at least

@@ -388,7 +388,7 @@ static int check_jammed(const sample_t *s, int64_t nkmers, const rsao_result_t *
 
 static int valid_desc(const rsao_desc_t *d)
 {
-    return d && d->k >= 1 && d->k <= d->L && d->L <= 32768 && (d->flags & ~(RSAO_FLAG_H_ONLY | RSAO_FLAG_TRACK_CLUSTERS)) == 0;
+    return d && d->k >= 1 && d->k <= d->L && d->L <= 32768 && (d->flags & ~(RSAO_FLAG_H_ONLY | RSAO_FLAG_TRACK_CLUSTERS | RSAO_FLAG_CONTACTS)) == 0;
 }
 
 /* One run, with optional extras for the contact census (out3 != NULL). */

@@ -47,6 +47,9 @@ extern "C" {
 /* Flag accepted for interface symmetry with the GPU library: the oracle
  * always takes the cluster census at jamming. */
 #define RSAO_FLAG_TRACK_CLUSTERS 2u
+/* Flag accepted for parity with the GPU descriptors (contact census wanted);
+ * the census itself comes from rsao_contacts_at_jamming. */
+#define RSAO_FLAG_CONTACTS 4u
 
 /* One independent run (Sec. II.A).  1 <= k <= L <= 32768. */
 typedef struct {

@@ -9,14 +9,12 @@
 
 namespace rsa {
 
-// persistent kernel of a schedule: (wave-count index, rows wider than 64
-// words, sparse clear)
-const void *persistent_kernel(int waves, int wide, int sparse)
+const void *persistent_kernel(int waves, int wide, int sparse, int census)
 {
-    static const void *(*const tables[kNumWaveTiles])[2] = {
+    static const void *(*const tables[kNumWaveTiles])[2][2] = {
         kPersistentKernelsW0, kPersistentKernelsW1, kPersistentKernelsW2, kPersistentKernelsW3,
         kPersistentKernelsW4};
-    return tables[waves][wide][sparse];
+    return tables[waves][wide][sparse][census];
 }
 
 int fail(rsa_ctx *c, int code, const std::string &msg)
@@ -36,7 +34,7 @@ int hip_fail(rsa_ctx *c, hipError_t e, const char *what)
 
 bool valid_sample(const rsa_sample_t &s)
 {
-    const uint32_t known = RSA_FLAG_H_ONLY | RSA_FLAG_TRACK_CLUSTERS;
+    const uint32_t known = RSA_FLAG_H_ONLY | RSA_FLAG_TRACK_CLUSTERS | RSA_FLAG_CONTACTS;
     return s.k >= 1 && s.k <= s.L && s.L <= 32768 && (s.flags & ~known) == 0;
 }
 
@@ -127,11 +125,11 @@ void give_block(rsa_ctx *c, Block b)
     if (b.ptr) c->pool.push_back(b);
 }
 
-int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, uint32_t lds)
+int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, int census, uint32_t lds)
 {
     int nb = 0;
     int threads = 64 * (kTileWaves[tile] + 1);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel(tile, wide, sparse), threads,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel(tile, wide, sparse, census), threads,
                                                      lds) !=
             hipSuccess ||
         nb < 1)
@@ -283,11 +281,13 @@ int rsa_create(rsa_ctx **out, int device, uint64_t hbm_budget_bytes, const rsa_a
     for (int t = 0; t < kNumWaveTiles; ++t) {
         for (int w = 0; w < 2; ++w) {
             for (int sp = 0; sp < 2; ++sp) {
-                if (hipFuncSetAttribute(persistent_kernel(t, w, sp),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)(c->lds_max - 64)) != hipSuccess) {
-                    delete c;
-                    return RSA_EDEVICE;
+                for (int cs = 0; cs < 2; ++cs) {
+                    if (hipFuncSetAttribute(persistent_kernel(t, w, sp, cs),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)(c->lds_max - 64)) != hipSuccess) {
+                        delete c;
+                        return RSA_EDEVICE;
+                    }
                 }
             }
         }
@@ -367,7 +367,8 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     std::vector<int> tiles(n), keys(n);
     for (uint32_t i = 0; i < n; ++i) {
         tiles[i] = sample_tile(c, s[i].L, s[i].k);
-        keys[i] = (tile_waves(tiles[i]) * 2 + (s[i].L > 4096 ? 1 : 0)) * 2 + tile_sparse(tiles[i]);
+        keys[i] = kernel_key(tile_waves(tiles[i]), s[i].L > 4096 ? 1 : 0, tile_sparse(tiles[i]),
+                             (s[i].flags & RSA_FLAG_CONTACTS) ? 1 : 0);
     }
     std::vector<uint32_t> order(n);
     for (uint32_t i = 0; i < n; ++i) order[i] = i;
@@ -378,16 +379,19 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     size_t total = 0;
     const size_t desc_bytes = align256((size_t)std::max<uint32_t>(n, 1) * sizeof(DevDesc));
     const size_t res_bytes = align256((size_t)std::max<uint32_t>(n, 1) * sizeof(DevResult));
-    const size_t queue_count = b->mode == RSA_MODE_PLAIN ? std::max<uint32_t>(n, 1) : 4 * kNumWaveTiles;
+    const size_t queue_count =
+        b->mode == RSA_MODE_PLAIN ? std::max<uint32_t>(n, 1) : (size_t)kKernelVariants * kNumWaveTiles;
     const size_t queue_bytes = align256(queue_count * 4);
     const size_t prof_words = c->opt_prof ? (size_t)std::max<uint32_t>(n, 1) * kProfSlots : 0;
     const size_t prof_bytes = align256(prof_words * 8);
     total = desc_bytes + res_bytes + queue_bytes + prof_bytes;
     for (uint32_t i = 0; i < n;) {
         Group g;
-        g.waves = keys[order[i]] >> 2;
-        g.wide = (keys[order[i]] >> 1) & 1;
-        g.sparse = keys[order[i]] & 1;
+        g.key = keys[order[i]];
+        g.waves = g.key >> 3;
+        g.wide = (g.key >> 2) & 1;
+        g.sparse = (g.key >> 1) & 1;
+        g.census = g.key & 1;
         g.first = i;
         uint32_t j = i;
         size_t stride = 0;
@@ -405,7 +409,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         if (b->mode == RSA_MODE_PLAIN) {
             grid = kPlainStreams;   // one slab per stream: samples on a stream run in order
         } else {
-            grid = std::min<uint32_t>(g.count, (uint32_t)resident_blocks(c, g.waves, g.wide, g.sparse, lds));
+            grid = std::min<uint32_t>(g.count, (uint32_t)resident_blocks(c, g.waves, g.wide, g.sparse, g.census, lds));
             if (c->opt_slots > 0) grid = std::min<uint32_t>(grid, (uint32_t)c->opt_slots);
         }
         g.grid = grid;
@@ -466,7 +470,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         a.descs = d_desc + g.first;
         a.n = g.count;
         a.tile = (uint32_t)g.waves;
-        a.queue = d_queue + (g.waves * 2 + g.wide) * 2 + g.sparse;
+        a.queue = d_queue + g.key;
         a.slabs = base + g.slab_off;
         a.slab_stride = g.stride;
         a.results = d_res;
@@ -498,7 +502,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
                 a.results = d_res;
                 a.prof = b->d_prof;
                 void *kargs[] = {&a};
-                HIP_TRY(c, hipLaunchKernel(persistent_kernel(g.waves, g.wide, g.sparse), dim3(1), dim3(threads), kargs,
+                HIP_TRY(c, hipLaunchKernel(persistent_kernel(g.waves, g.wide, g.sparse, g.census), dim3(1), dim3(threads), kargs,
                                            g.lds, c->plain[si]));
             }
         }
@@ -513,11 +517,11 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         for (size_t i = 0; i < args.size(); ++i) {
             const Group &g = b->groups[i];
             char buf[64];
-            std::snprintf(buf, sizeof(buf), "%d:%d:%d:%u:%u|", g.waves, g.wide, g.sparse, g.grid, g.lds);
+            std::snprintf(buf, sizeof(buf), "%d:%u:%u|", g.key, g.grid, g.lds);
             key += buf;
             key.append((const char *)&args[i], sizeof(KernelArgs));
         }
-        uint32_t nq = 4 * kNumWaveTiles;
+        uint32_t nq = kKernelVariants * kNumWaveTiles;
         if (c->opt_graph) {
             hipGraphExec_t exec = cached_graph(c, key);
             if (!exec) {
@@ -537,7 +541,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
                     hipKernelNodeParams kp;
                     std::memset(&kp, 0, sizeof(kp));
                     void *kargs[] = {&args[i]};
-                    kp.func = (void *)persistent_kernel(g.waves, g.wide, g.sparse);
+                    kp.func = (void *)persistent_kernel(g.waves, g.wide, g.sparse, g.census);
                     kp.gridDim = dim3(g.grid);
                     kp.blockDim = dim3(64 * (kTileWaves[g.waves] + 1));
                     kp.sharedMemBytes = g.lds;
@@ -561,7 +565,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
             for (size_t i = 0; i < args.size(); ++i) {
                 const Group &g = b->groups[i];
                 void *kargs[] = {&args[i]};
-                HIP_TRY(c, hipLaunchKernel(persistent_kernel(g.waves, g.wide, g.sparse), dim3(g.grid),
+                HIP_TRY(c, hipLaunchKernel(persistent_kernel(g.waves, g.wide, g.sparse, g.census), dim3(g.grid),
                                            dim3(64 * (kTileWaves[g.waves] + 1)), kargs, g.lds, stream));
             }
         }

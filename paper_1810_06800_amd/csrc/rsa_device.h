@@ -58,13 +58,14 @@ struct DevDesc {
     FastDiv fwp;       // division by the padded row words
 };
 
-// Mirrors rsa_result_t of include/rsa.h (80 bytes).
+// Mirrors rsa_result_t of include/rsa.h (104 bytes).
 struct DevResult {
     int64_t n_jam, n_wrap_x, n_wrap_y, n_wrap_any;
     uint64_t occ_hash, seq_hash;
     int32_t n_clusters_jam, n_nonwrapping_jam;
     int32_t status, tile;
     uint64_t alg_bytes, wchg_words;
+    int64_t n_contacts_x, n_contacts_y, n_contacts_xy;
 };
 
 // Fixed capacities of the per-workgroup LDS areas.

@@ -173,6 +173,8 @@ struct Hdr {
     uint32_t resumed;        // state restored from the slab
     uint32_t preempt;        // the selecting wave stopped at its deadline
     uint32_t lab_stop;       // labelling ended early (both wrap steps known)
+    uint32_t pad2;
+    unsigned long long ncon[3];   // contact census: both H, both V, perpendicular
 };
 
 struct Ctx {
@@ -1423,6 +1425,65 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track)
 }
 
 // ---------------------------------------------------------------------------
+// Contact census at jamming (Eq. 12)
+// ---------------------------------------------------------------------------
+
+// Every site and its right and lower neighbour (mod L): a pair of occupied
+// sites in different k-mers counts as both horizontal, both vertical or
+// perpendicular (orientation from the k-mer records).  The workgroup walks
+// the map tile by tile in memory order, 32 lanes per 128-byte tile and
+// kCensusUnroll tiles per lane group in flight.
+constexpr uint32_t kCensusUnroll = 4;
+
+template <uint32_t NT>
+__device__ __forceinline__ void contact_census(const Ctx &c, uint32_t tid)
+{
+    const uint32_t L = c.L;
+    const uint32_t groups = NT / 32;            // tiles per pass
+    const uint32_t grp = tid >> 5, off = tid & 31;
+    const uint32_t oy = off >> c.lg_mc, ox = off & c.mc_m;
+    const uint32_t ntr = c.lp >> c.lg_mr;       // tile rows
+    const uint32_t ntiles = ntr * c.mtpr;
+    uint32_t n[3] = {0, 0, 0};
+    for (uint32_t t0 = 0; t0 < ntiles; t0 += groups * kCensusUnroll) {
+        int32_t a[kCensusUnroll], br[kCensusUnroll], bd[kCensusUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kCensusUnroll; ++u) {
+            const uint32_t tile = t0 + u * groups + grp;
+            a[u] = br[u] = bd[u] = -1;
+            if (tile < ntiles) {
+                const uint32_t tr = tile / c.mtpr, tc = tile - tr * c.mtpr;
+                const uint32_t y = (tr << c.lg_mr) + oy, x = (tc << c.lg_mc) + ox;
+                if (y < L && x < L) {
+                    a[u] = c.map[((size_t)tile << 5) + off];
+                    const uint32_t xr = x + 1 == L ? 0 : x + 1, yd = y + 1 == L ? 0 : y + 1;
+                    br[u] = c.map[map_index(c, y, xr)];
+                    bd[u] = c.map[map_index(c, yd, x)];
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kCensusUnroll; ++u) {
+            if (a[u] < 0) continue;
+            const uint32_t oa = c.kmer[a[u]] >> 31;
+            if (br[u] >= 0 && br[u] != a[u]) {
+                const uint32_t ob = c.kmer[br[u]] >> 31;
+                ++n[oa != ob ? 2 : oa];
+            }
+            if (bd[u] >= 0 && bd[u] != a[u]) {
+                const uint32_t ob = c.kmer[bd[u]] >> 31;
+                ++n[oa != ob ? 2 : oa];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const uint32_t w = wave_sum32(n[j]);
+        if ((tid & 63) == 0 && w) atomicAdd(&c.h->ncon[j], (unsigned long long)w);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One sample, then the persistent loop
 // ---------------------------------------------------------------------------
 
@@ -1492,7 +1553,7 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
 // slab is the sample's own and holds a SampleState: a finished sample
 // re-emits its result, a yielded one restores its row counts and header and
 // continues, and the run yields again at the deadline, saving them back.
-template <int NSEL, int ROWW, bool SPARSE>
+template <int NSEL, int ROWW, bool SPARSE, bool CENSUS>
 __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d, uint8_t *lds,
                                            uint64_t deadline)
 {
@@ -1507,6 +1568,9 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
     const uint32_t L = c.L;
     const bool h_only = (c.flags & 1u) != 0;
     const bool track = (c.flags & 2u) != 0;
+    // the contact census is compiled only into the CENSUS kernels, so that
+    // the others keep their register allocation
+    const bool contacts = CENSUS && (c.flags & 4u) != 0;
     const bool sliced = deadline != 0;
     SampleState *st = (SampleState *)(slab + slab_layout(d.L, d.k).state);
     uint32_t *saved_cnt = (uint32_t *)((uint8_t *)st + kStateBytes);
@@ -1545,6 +1609,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             h->resumed = 1;
             h->preempt = 0;
             h->lab_stop = st->lab_stop;
+            h->ncon[0] = h->ncon[1] = h->ncon[2] = 0;
         }
     } else {
         // ---- initial state (Sec. II.A): all sites empty, all placements free
@@ -1616,6 +1681,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             h->resumed = 0;
             h->preempt = 0;
             h->lab_stop = 0;
+            h->ncon[0] = h->ncon[1] = h->ncon[2] = 0;
         }
     }
     __syncthreads();
@@ -1627,7 +1693,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
     else if (wave < (uint32_t)NSEL)
         helper<NSEL, SPARSE>(c, wave);
     else
-        labeler<(NSEL >= 7 ? 16 : 8)>(c, track);
+        labeler<(NSEL >= 7 ? 16 : 8)>(c, track || contacts);
     __syncthreads();
 
     if (c.h->preempt && c.h->status == 0) {
@@ -1660,10 +1726,19 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             r.tile = (int32_t)d.tile;
             r.alg_bytes = 0;
             r.wchg_words = h->wchg;
+            r.n_contacts_x = r.n_contacts_y = r.n_contacts_xy = -1;
             a.results[d.out] = r;
         }
         __syncthreads();
         return;
+    }
+
+    // ---- contact census at jamming (Eq. 12)
+    if constexpr (CENSUS) {
+        if (contacts && c.h->status == 0) {
+            contact_census<NT>(c, tid);
+            __syncthreads();
+        }
     }
 
     // ---- cluster census at jamming (Appendix A)
@@ -1700,6 +1775,9 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
         r.wchg_words = c.h->wchg;
         r.alg_bytes = 4 * Lw * Lw + 16 * Lw * c.wd +
                       (uint64_t)njam * (4 * kw + 4 * (2 * kw + 2) + 8 * c.wd + 16) + 16 * r.wchg_words;
+        r.n_contacts_x = contacts ? (int64_t)c.h->ncon[0] : -1;
+        r.n_contacts_y = contacts ? (int64_t)c.h->ncon[1] : -1;
+        r.n_contacts_xy = contacts ? (int64_t)c.h->ncon[2] : -1;
         a.results[d.out] = r;
         if (sliced) {
             st->result = r;
@@ -1709,7 +1787,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
     __syncthreads();
 }
 
-template <int NSEL, int ROWW, bool SPARSE>
+template <int NSEL, int ROWW, bool SPARSE, bool CENSUS>
 __global__ __launch_bounds__(64 * (NSEL + 1)) void rsa_persistent(KernelArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -1724,7 +1802,7 @@ __global__ __launch_bounds__(64 * (NSEL + 1)) void rsa_persistent(KernelArgs a)
         __syncthreads();
         if (i >= a.n) return;
         const DevDesc d = a.descs[i];
-        run_sample<NSEL, ROWW, SPARSE>(a, d, lds, deadline);
+        run_sample<NSEL, ROWW, SPARSE, CENSUS>(a, d, lds, deadline);
     }
 }
 
@@ -1756,19 +1834,20 @@ __global__ void rsa_prepare_launch(const DevDesc *descs, uint32_t n, DevResult *
 }  // namespace rsa
 
 // Host-visible launch table of this translation unit:
-// [row words per lane 1 or 8][dense, sparse] for one wave count.  The library
-// compiles this file once per wave-count index (RSA_TU_WAVES = 0 ..
-// kNumWaveTiles - 1) so that the instantiations build in parallel.
+// [row words per lane 1 or 8][dense, sparse][without, with contact census]
+// for one wave count.  The library compiles this file once per wave-count
+// index (RSA_TU_WAVES = 0 .. kNumWaveTiles - 1) so that the instantiations
+// build in parallel.
 #define RSA_CAT2(a, b) a##b
 #define RSA_CAT(a, b) RSA_CAT2(a, b)
 #define RSA_TABLE RSA_CAT(kPersistentKernelsW, RSA_TU_WAVES)
+#define RSA_KP(ROWW, SPARSE, CENSUS) \
+    (const void *)&rsa_persistent<kTileWaves[RSA_TU_WAVES], ROWW, SPARSE, CENSUS>
 namespace rsa {
-extern const void *RSA_TABLE[2][2];
-const void *RSA_TABLE[2][2] = {
-    {(const void *)&rsa_persistent<kTileWaves[RSA_TU_WAVES], 1, false>,
-     (const void *)&rsa_persistent<kTileWaves[RSA_TU_WAVES], 1, true>},
-    {(const void *)&rsa_persistent<kTileWaves[RSA_TU_WAVES], 8, false>,
-     (const void *)&rsa_persistent<kTileWaves[RSA_TU_WAVES], 8, true>}};
+extern const void *RSA_TABLE[2][2][2];
+const void *RSA_TABLE[2][2][2] = {
+    {{RSA_KP(1, false, false), RSA_KP(1, false, true)}, {RSA_KP(1, true, false), RSA_KP(1, true, true)}},
+    {{RSA_KP(8, false, false), RSA_KP(8, false, true)}, {RSA_KP(8, true, false), RSA_KP(8, true, true)}}};
 #if RSA_TU_WAVES == 0
 extern const void *kResetKernel;
 extern const void *kPrepareKernel;

@@ -19,22 +19,28 @@
 
 namespace rsa {
 // launch tables of the kernel translation units, one per wave count
-extern const void *kPersistentKernelsW0[2][2];
-extern const void *kPersistentKernelsW1[2][2];
-extern const void *kPersistentKernelsW2[2][2];
-extern const void *kPersistentKernelsW3[2][2];
-extern const void *kPersistentKernelsW4[2][2];
+extern const void *kPersistentKernelsW0[2][2][2];
+extern const void *kPersistentKernelsW1[2][2][2];
+extern const void *kPersistentKernelsW2[2][2][2];
+extern const void *kPersistentKernelsW3[2][2][2];
+extern const void *kPersistentKernelsW4[2][2][2];
 extern const void *kResetKernel;
 extern const void *kPrepareKernel;
 static_assert(kNumWaveTiles == 5, "one launch table per wave count");
 
 // persistent kernel of a schedule: (wave-count index, rows wider than 64
-// words, sparse clear)
-const void *persistent_kernel(int waves, int wide, int sparse);
+// words, sparse clear, contact census compiled in)
+const void *persistent_kernel(int waves, int wide, int sparse, int census);
+// Kernel variants per wave count: wide x sparse x census.
+constexpr int kKernelVariants = 8;
+inline int kernel_key(int waves, int wide, int sparse, int census)
+{
+    return ((waves * 2 + wide) * 2 + sparse) * 2 + census;
+}
 }  // namespace rsa
 
 static_assert(sizeof(rsa_result_t) == sizeof(rsa::DevResult), "result layout");
-static_assert(sizeof(rsa_result_t) == 80, "result size");
+static_assert(sizeof(rsa_result_t) == 104, "result size");
 static_assert(sizeof(rsa_sample_t) == 24, "sample size");
 
 namespace rsa {
@@ -42,9 +48,11 @@ namespace rsa {
 constexpr int kPlainStreams = 4;
 
 struct Group {
-    int waves;               // index into kTileWaves (the kernel instantiation)
+    int key;                 // kernel_key of the instantiation
+    int waves;               // index into kTileWaves
     int wide;                // rows of more than 64 words (L > 4096)
     int sparse;              // clear mode
+    int census;              // contact census compiled in
     uint32_t first, count;   // range in the planned descriptor array
     uint32_t grid;
     uint32_t lds;
@@ -114,7 +122,7 @@ int sample_tile(const rsa_ctx *c, uint32_t L, uint32_t k);
 bool take_block(rsa_ctx *c, size_t bytes, Block &out);
 void give_block(rsa_ctx *c, Block b);
 // Workgroups of a schedule's kernel resident on the whole device at once.
-int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, uint32_t lds);
+int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, int census, uint32_t lds);
 // Kernel-side descriptor of a sample; `out` is its index in the result array.
 DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile);
 

@@ -27,7 +27,7 @@ constexpr int kStreams = 4;          // group launches fork onto these
 constexpr int kDepth = 2;            // launches in flight
 constexpr uint32_t kDefaultQuantumUs = 2000;
 constexpr uint32_t kDefaultResident = 4096;
-constexpr uint32_t kQueueWords = 64;   // one counter per kernel group (at most 40 groups)
+constexpr uint32_t kQueueWords = 128;  // one counter per kernel group (at most 80 groups)
 constexpr size_t kLookahead = 256;     // queued samples scanned past one that does not fit
 
 struct Sample {
@@ -96,12 +96,14 @@ namespace {
 
 uint32_t lds_bytes(uint32_t L) { return lds_layout(L).total; }
 
-// Kernel group of a sample: (waves, rows wider than 64 words, sparse clear)
-// select the kernel; the last bit splits lattices up to L = 1024 from larger
-// ones, whose row counts take more LDS and so fewer workgroups per CU.
+// Kernel group of a sample: (waves, rows wider than 64 words, sparse clear,
+// contact census) select the kernel; the last bit splits lattices up to
+// L = 1024 from larger ones, whose row counts take more LDS and so fewer
+// workgroups per CU.
 int group_key(const rsa_sample_t &s, int tile)
 {
-    const int kernel = (tile_waves(tile) * 2 + (s.L > 4096 ? 1 : 0)) * 2 + tile_sparse(tile);
+    const int kernel = kernel_key(tile_waves(tile), s.L > 4096 ? 1 : 0, tile_sparse(tile),
+                                  (s.flags & RSA_FLAG_CONTACTS) ? 1 : 0);
     return kernel * 2 + (s.L > 1024 ? 1 : 0);
 }
 
@@ -231,7 +233,7 @@ int launch(rsa_server *v)
     // samples up to what fits on the device, scaled down together when the
     // groups would not all be resident at once
     struct G {
-        int kern;   // (waves * 2 + wide) * 2 + sparse
+        int kern;   // kernel_key
         uint32_t first, count, lds, cap, grid;
     };
     std::vector<G> gs;
@@ -243,8 +245,8 @@ int launch(rsa_server *v)
             ++j;
         }
         const int kern = key >> 1;
-        const int waves = kern >> 2, wide = (kern >> 1) & 1, sparse = kern & 1;
-        uint32_t cap = (uint32_t)resident_blocks(c, waves, wide, sparse, lds);
+        const int waves = kern >> 3, wide = (kern >> 2) & 1, sparse = (kern >> 1) & 1, census = kern & 1;
+        uint32_t cap = (uint32_t)resident_blocks(c, waves, wide, sparse, census, lds);
         gs.push_back(G{kern, i, j - i, lds, cap, 0});
         i = j;
     }
@@ -273,7 +275,8 @@ int launch(rsa_server *v)
     for (int s = 0; s < kStreams; ++s) HIP_TRY(c, hipStreamWaitEvent(v->streams[s], v->fork, 0));
     for (size_t gi = 0; gi < gs.size(); ++gi) {
         const G &g = gs[gi];
-        const int waves = g.kern >> 2, wide = (g.kern >> 1) & 1, sparse = g.kern & 1;
+        const int waves = g.kern >> 3, wide = (g.kern >> 2) & 1, sparse = (g.kern >> 1) & 1,
+                  census = g.kern & 1;
         KernelArgs a{};
         a.descs = b.d_desc + g.first;
         a.n = g.count;
@@ -285,7 +288,7 @@ int launch(rsa_server *v)
         a.prof = nullptr;
         a.quantum = v->quantum_ticks;
         void *kargs[] = {&a};
-        HIP_TRY(c, hipLaunchKernel(persistent_kernel(waves, wide, sparse), dim3(g.grid),
+        HIP_TRY(c, hipLaunchKernel(persistent_kernel(waves, wide, sparse, census), dim3(g.grid),
                                    dim3(64 * (kTileWaves[waves] + 1)), kargs, g.lds,
                                    v->streams[gi % kStreams]));
     }

@@ -21,6 +21,7 @@ RSA_OK, RSA_EINVAL, RSA_ENOMEM, RSA_EDEVICE, RSA_ENOTREADY, RSA_EBUSY, RSA_ENOTF
     0, -1, -2, -3, -4, -5, -6)
 FLAG_H_ONLY = 1
 FLAG_TRACK_CLUSTERS = 2
+FLAG_CONTACTS = 4
 OPT_MODE, OPT_TILE, OPT_GRAPH, OPT_SLOTS, OPT_PROFILE = 1, 2, 3, 4, 5
 PROFILE_SLOTS = ("init", "sel_total", "sel_ring", "sel_select", "sel_clear", "lab_total", "lab_idle",
                  "lab_map", "lab_gather", "lab_resolve", "lab_merge", "lab_writeback",
@@ -47,7 +48,9 @@ class Result(ctypes.Structure):
                 ("occ_hash", ctypes.c_uint64), ("seq_hash", ctypes.c_uint64),
                 ("n_clusters_jam", ctypes.c_int32), ("n_nonwrapping_jam", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("alg_bytes", ctypes.c_uint64), ("wchg_words", ctypes.c_uint64)]
+                ("alg_bytes", ctypes.c_uint64), ("wchg_words", ctypes.c_uint64),
+                ("n_contacts_x", ctypes.c_int64), ("n_contacts_y", ctypes.c_int64),
+                ("n_contacts_xy", ctypes.c_int64)]
 
 
 RESULT_FIELDS = [name for name, _ in Result._fields_]

@@ -35,6 +35,14 @@ def test_every_declared_symbol_is_exported(rsa):
     assert set(names) == set(rsa.EXPORTS)
 
 
+def test_record_layouts(rsa):
+    import ctypes
+
+    assert ctypes.sizeof(rsa.Sample) == 24
+    assert ctypes.sizeof(rsa.Result) == 104
+    assert ctypes.sizeof(rsa.ServerConfig) == 16
+
+
 def test_footprint_matches_layout(rsa):
     # two bitmaps of L*ceil(L/64) words, int32 map, 20 B per k-mer record,
     # every area 256-byte aligned

@@ -218,10 +218,32 @@ def test_autotune_table_applied(ctx, orc):
     assert ctx.tile_for_sample(2048, 128) == table[(2048, 128)]   # table unchanged
 
 
+def test_contact_census(ctx, orc):
+    """RSA_FLAG_CONTACTS: the census of the jammed state (Eq. 12) against the
+    oracle's, on tiny tori, ragged and wide lattices, rings and one full
+    L = 1024, k = 64 sample; the other fields are unchanged by the flag."""
+    from paper_1810_06800_amd import rsa
+
+    descs = [(L, k, 3, s, 4) for L in (1, 2, 3, 5, 8) for k in range(1, L + 1) for s in range(2)]
+    descs += [(64, 8, 1, s, 4) for s in range(4)] + [(200, 20, 3, 1, 6), (130, 65, 4, 4, 4),
+                                                      (96, 4, 9, 0, 5), (300, 7, 8, 2, 4),
+                                                      (4160, 64, 7, 0, 4), (1024, 64, 2, 0, 4)]
+    _log(f"contact census: {len(descs)} samples")
+    got = ctx.run(descs)
+    check(descs, got, orc.run_many(descs, threads=min(16, os.cpu_count() or 1)), census=True)
+    for d, g in zip(descs, got):
+        want = orc.contacts_at_jamming(*d)
+        assert (g["n_contacts_x"], g["n_contacts_y"], g["n_contacts_xy"]) == want, d
+    plain = ctx.run([d[:4] + (d[4] & ~rsa.FLAG_CONTACTS,) for d in descs[-3:]])
+    for g, p in zip(got[-3:], plain):
+        assert p["n_contacts_x"] == -1
+        assert all(g[f] == p[f] for f in FIELDS)
+
+
 def test_invalid_descriptors_rejected(ctx):
     from paper_1810_06800_amd import rsa
 
-    for bad in [(4, 5, 0, 0, 0), (0, 0, 0, 0, 0), (32769, 8, 0, 0, 0), (16, 4, 0, 0, 8)]:
+    for bad in [(4, 5, 0, 0, 0), (0, 0, 0, 0, 0), (32769, 8, 0, 0, 0), (16, 4, 0, 0, 16)]:
         with pytest.raises(rsa.RsaError) as e:
             ctx.run_batch([bad])
         assert e.value.code == rsa.RSA_EINVAL
