@@ -66,8 +66,17 @@ enum rsa_flags {
      * nearest-neighbour sites in different k-mers, both horizontal, both
      * vertical or perpendicular.  Keeps the site map written to jamming and
      * adds one pass over it. */
-    RSA_FLAG_CONTACTS = 1u << 2
+    RSA_FLAG_CONTACTS = 1u << 2,
+    /* rsa_run_batch only: also histogram the cluster sizes right after
+     * deposit n_wrap_any, the percolation threshold (Eq. 11: n_s at p_c);
+     * read them with rsa_batch_cluster_sizes.  The sample is run a second
+     * time, inside the same batch, up to that deposit. */
+    RSA_FLAG_CLUSTER_SIZES = 1u << 3
 };
+
+/* Bins of a cluster-size histogram: bin b counts the clusters whose size in
+ * sites s satisfies 2^b <= s < 2^(b+1). */
+#define RSA_SIZE_BINS 32
 
 /* Opaque context.  Owns every device allocation made on its behalf. */
 typedef struct rsa_ctx rsa_ctx;
@@ -177,6 +186,16 @@ int rsa_batch_elapsed_ms(rsa_ctx *ctx, uint64_t batch_id, float *ms);
  * not profiled or n differs from its size. */
 int rsa_batch_profile(rsa_ctx *ctx, uint64_t batch_id, uint64_t *out, uint32_t n,
                       uint32_t *slots, uint32_t *clock_khz);
+
+/* Cluster-size histograms of batch `batch_id` (RSA_FLAG_CLUSTER_SIZES):
+ * out[i * RSA_SIZE_BINS + b], i in descriptor order, = the number of clusters
+ * of sample i with 2^b <= size in sites < 2^(b+1), over the whole lattice
+ * right after deposit n_wrap_any (n_s at the percolation threshold, Eq. 11,
+ * is bin / (L*L) after averaging over samples).  Samples without the flag
+ * read all zero; a sample whose rerun failed reads all ones.  Blocks until
+ * the batch's kernels are done; valid until rsa_results.  RSA_EINVAL if no
+ * sample of the batch has the flag or n differs from its size. */
+int rsa_batch_cluster_sizes(rsa_ctx *ctx, uint64_t batch_id, uint64_t *out, uint32_t n);
 
 /* Wait for all work of the context, free every allocation and the context.
  * NULL is ignored. */
@@ -291,8 +310,9 @@ int rsa_server_create(rsa_ctx *ctx, const rsa_server_config_t *cfg, void *hip_st
 /* Queue a request of n samples (copied; the caller keeps `samples`) and
  * return its id in *request_id.  Nothing is launched here; rsa_server_step
  * admits and runs.  RSA_EINVAL (nothing queued) for n == 0, an invalid
- * descriptor, or one whose row counts do not fit a workgroup's LDS;
- * RSA_ENOMEM if one sample alone needs more than the arena. */
+ * descriptor, RSA_FLAG_CLUSTER_SIZES (a batch feature), or a descriptor whose
+ * row counts do not fit a workgroup's LDS; RSA_ENOMEM if one sample alone
+ * needs more than the arena. */
 int rsa_server_submit(rsa_server *srv, const rsa_sample_t *samples, uint32_t n,
                       uint64_t *request_id);
 

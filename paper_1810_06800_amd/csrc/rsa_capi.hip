@@ -34,7 +34,7 @@ int hip_fail(rsa_ctx *c, hipError_t e, const char *what)
 
 bool valid_sample(const rsa_sample_t &s)
 {
-    const uint32_t known = RSA_FLAG_H_ONLY | RSA_FLAG_TRACK_CLUSTERS | RSA_FLAG_CONTACTS;
+    const uint32_t known = RSA_FLAG_H_ONLY | RSA_FLAG_TRACK_CLUSTERS | RSA_FLAG_CONTACTS | RSA_FLAG_CLUSTER_SIZES;
     return s.k >= 1 && s.k <= s.L && s.L <= 32768 && (s.flags & ~known) == 0;
 }
 
@@ -362,32 +362,52 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     b->n = n;
     b->mode = (int)c->opt_mode;
 
-    // ---- plan: group by tile, longest samples first inside a group
-    // group key: (wave count, rows wider than 64 words, clear mode) -> kernel
-    std::vector<int> tiles(n), keys(n);
+    // ---- plan: group by tile, longest samples first inside a group.
+    // Entries 0..n-1 are the runs; a sample with RSA_FLAG_CLUSTER_SIZES gets a
+    // second-pass entry after them (rerun to its first wrap, then histogram).
+    // Group key: (pass, wave count, rows wider than 64 words, clear mode,
+    // statistics compiled in) -> kernel.
+    std::vector<int> tiles(n);
+    std::vector<uint32_t> ent_sample, ent_pass;
+    std::vector<int> keys;
     for (uint32_t i = 0; i < n; ++i) {
         tiles[i] = sample_tile(c, s[i].L, s[i].k);
-        keys[i] = kernel_key(tile_waves(tiles[i]), s[i].L > 4096 ? 1 : 0, tile_sparse(tiles[i]),
-                             (s[i].flags & RSA_FLAG_CONTACTS) ? 1 : 0);
+        ent_sample.push_back(i);
+        ent_pass.push_back(0);
+        keys.push_back(kernel_key(tile_waves(tiles[i]), s[i].L > 4096 ? 1 : 0, tile_sparse(tiles[i]),
+                                  (s[i].flags & RSA_FLAG_CONTACTS) ? 1 : 0));
     }
-    std::vector<uint32_t> order(n);
-    for (uint32_t i = 0; i < n; ++i) order[i] = i;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!(s[i].flags & RSA_FLAG_CLUSTER_SIZES)) continue;
+        ent_sample.push_back(i);
+        ent_pass.push_back(1);
+        keys.push_back(kernel_key(tile_waves(tiles[i]), s[i].L > 4096 ? 1 : 0, tile_sparse(tiles[i]), 1));
+    }
+    const uint32_t ne = (uint32_t)ent_sample.size();
+    const bool sizes = ne > n;
+    std::vector<uint32_t> order(ne);
+    for (uint32_t i = 0; i < ne; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t bb) {
+        if (ent_pass[a] != ent_pass[bb]) return ent_pass[a] < ent_pass[bb];
         if (keys[a] != keys[bb]) return keys[a] > keys[bb];
-        return sample_cost(s[a].L, s[a].k, tiles[a]) > sample_cost(s[bb].L, s[bb].k, tiles[bb]);
+        const rsa_sample_t &x = s[ent_sample[a]], &y = s[ent_sample[bb]];
+        return sample_cost(x.L, x.k, tiles[ent_sample[a]]) > sample_cost(y.L, y.k, tiles[ent_sample[bb]]);
     });
     size_t total = 0;
-    const size_t desc_bytes = align256((size_t)std::max<uint32_t>(n, 1) * sizeof(DevDesc));
+    const size_t nq_batched = (size_t)2 * kKernelVariants * kNumWaveTiles;   // per pass and kernel
+    const size_t desc_bytes = align256((size_t)std::max<uint32_t>(ne, 1) * sizeof(DevDesc));
     const size_t res_bytes = align256((size_t)std::max<uint32_t>(n, 1) * sizeof(DevResult));
-    const size_t queue_count =
-        b->mode == RSA_MODE_PLAIN ? std::max<uint32_t>(n, 1) : (size_t)kKernelVariants * kNumWaveTiles;
+    const size_t queue_count = b->mode == RSA_MODE_PLAIN ? std::max<uint32_t>(n, 1) + nq_batched : nq_batched;
     const size_t queue_bytes = align256(queue_count * 4);
     const size_t prof_words = c->opt_prof ? (size_t)std::max<uint32_t>(n, 1) * kProfSlots : 0;
     const size_t prof_bytes = align256(prof_words * 8);
-    total = desc_bytes + res_bytes + queue_bytes + prof_bytes;
-    for (uint32_t i = 0; i < n;) {
+    const size_t hist_words = sizes ? (size_t)n * kSizeBins : 0;
+    const size_t hist_bytes = align256(hist_words * 8);
+    total = desc_bytes + res_bytes + queue_bytes + prof_bytes + hist_bytes;
+    for (uint32_t i = 0; i < ne;) {
         Group g;
         g.key = keys[order[i]];
+        g.pass = (int)ent_pass[order[i]];
         g.waves = g.key >> 3;
         g.wide = (g.key >> 2) & 1;
         g.sparse = (g.key >> 1) & 1;
@@ -396,9 +416,10 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         uint32_t j = i;
         size_t stride = 0;
         uint32_t lds = 0;
-        while (j < n && keys[order[j]] == keys[order[i]]) {
-            stride = std::max(stride, slab_layout(s[order[j]].L, s[order[j]].k).total);
-            lds = std::max(lds, lds_layout(s[order[j]].L).total);
+        while (j < ne && keys[order[j]] == keys[order[i]] && ent_pass[order[j]] == ent_pass[order[i]]) {
+            const rsa_sample_t &x = s[ent_sample[order[j]]];
+            stride = std::max(stride, slab_layout(x.L, x.k).total);
+            lds = std::max(lds, lds_layout(x.L).total);
             ++j;
         }
         g.count = j - i;
@@ -406,7 +427,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         g.lds = lds;
         if (lds + 64 > c->lds_max) return fail(c, RSA_EINVAL, "lattice too large for LDS");
         uint32_t grid;
-        if (b->mode == RSA_MODE_PLAIN) {
+        if (b->mode == RSA_MODE_PLAIN && g.pass == 0) {
             grid = kPlainStreams;   // one slab per stream: samples on a stream run in order
         } else {
             grid = std::min<uint32_t>(g.count, (uint32_t)resident_blocks(c, g.waves, g.wide, g.sparse, g.census, lds));
@@ -430,16 +451,32 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         if (!big) return fail(c, RSA_ENOMEM, "batch does not fit the device memory budget");
         big->grid = std::max<uint32_t>(1, big->grid / 2);
     }
-    for (auto &g : b->groups) {
-        g.slab_off = total;
-        total += g.stride * g.grid;
+    // the second pass starts after the first has finished, so its groups
+    // reuse the first pass's slabs where they are large enough
+    std::vector<Group *> pass0, pass1;
+    for (auto &g : b->groups) (g.pass ? pass1 : pass0).push_back(&g);
+    const size_t slab_base = total;
+    for (auto *g : pass0) {
+        g->slab_off = total;
+        total += g->stride * g->grid;
     }
+    {
+        size_t off = slab_base;
+        for (auto *g : pass1) {
+            g->slab_off = off;
+            off += g->stride * g->grid;
+        }
+        total = std::max(total, off);
+    }
+    if (total > c->budget) return fail(c, RSA_ENOMEM, "batch does not fit the device memory budget");
     if (!take_block(c, total, b->mem)) return fail(c, RSA_ENOMEM, "device allocation failed");
     uint8_t *base = (uint8_t *)b->mem.ptr;
     DevDesc *d_desc = (DevDesc *)base;
     DevResult *d_res = (DevResult *)(base + desc_bytes);
     uint32_t *d_queue = (uint32_t *)(base + desc_bytes + res_bytes);
     b->d_prof = prof_words ? (unsigned long long *)(base + desc_bytes + res_bytes + queue_bytes) : nullptr;
+    b->d_hist = hist_words ? (unsigned long long *)(base + desc_bytes + res_bytes + queue_bytes + prof_bytes)
+                           : nullptr;
 
     // ---- descriptors (pinned staging), copied before the call returns
     if (hipHostMalloc((void **)&b->h_desc, desc_bytes, hipHostMallocDefault) != hipSuccess ||
@@ -447,12 +484,16 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         destroy_batch(c, b.release());
         return fail(c, RSA_ENOMEM, "pinned host allocation failed");
     }
-    for (uint32_t i = 0; i < n; ++i) b->h_desc[i] = make_dev_desc(s[order[i]], order[i], tiles[order[i]]);
+    for (uint32_t i = 0; i < ne; ++i) {
+        const uint32_t si = ent_sample[order[i]];
+        b->h_desc[i] = make_dev_desc(s[si], si, tiles[si]);
+        if (ent_pass[order[i]]) b->h_desc[i].flags |= kDescSizesPass;
+    }
     HIP_TRY(c, hipEventCreate(&b->ev_start));
     HIP_TRY(c, hipEventCreate(&b->ev_end));
     HIP_TRY(c, hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
-    if (n > 0)
-        HIP_TRY(c, hipMemcpyAsync(d_desc, b->h_desc, (size_t)n * sizeof(DevDesc),
+    if (ne > 0)
+        HIP_TRY(c, hipMemcpyAsync(d_desc, b->h_desc, (size_t)ne * sizeof(DevDesc),
                                   hipMemcpyHostToDevice, stream));
 
     // ---- launches
@@ -463,32 +504,46 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         void *zargs[] = {&pw, &words};
         HIP_TRY(c, hipLaunchKernel(kResetKernel, dim3((words + 255) / 256), dim3(256), zargs, 0, stream));
     }
+    if (b->d_hist) {
+        // histograms of samples without the flag read as zero
+        uint32_t words = (uint32_t)(hist_words * 2);
+        uint32_t *hw = (uint32_t *)b->d_hist;
+        void *zargs[] = {&hw, &words};
+        HIP_TRY(c, hipLaunchKernel(kResetKernel, dim3((words + 255) / 256), dim3(256), zargs, 0, stream));
+    }
     HIP_TRY(c, hipEventRecord(b->ev_start, stream));
+    // queue counters: the plain form's per-sample counters first, then one
+    // per (pass, kernel) for the persistent launches
+    const size_t qbase = b->mode == RSA_MODE_PLAIN ? std::max<uint32_t>(n, 1) : 0;
     std::vector<KernelArgs> args;
     for (auto &g : b->groups) {
         KernelArgs a{};
         a.descs = d_desc + g.first;
         a.n = g.count;
         a.tile = (uint32_t)g.waves;
-        a.queue = d_queue + g.key;
+        a.queue = d_queue + qbase + (size_t)g.pass * kKernelVariants * kNumWaveTiles + g.key;
         a.slabs = base + g.slab_off;
         a.slab_stride = g.stride;
         a.results = d_res;
-        a.prof = b->d_prof;
+        a.prof = g.pass ? nullptr : b->d_prof;   // counters describe the runs, not the reruns
+        a.hist = b->d_hist;
         args.push_back(a);
     }
+    uint32_t nq = (uint32_t)queue_count;
+    void *rargs[] = {&d_queue, &nq};
+    const dim3 rgrid((nq + 255) / 256), rblock(256);
     if (n == 0) {
         // nothing to run
     } else if (b->mode == RSA_MODE_PLAIN) {
         // one launch per sample, round-robin over four streams forked from
-        // the caller's stream; one slab per stream
-        uint32_t nq = (uint32_t)queue_count;
-        void *rargs[] = {&d_queue, &nq};
-        HIP_TRY(c, hipLaunchKernel(kResetKernel, dim3((nq + 255) / 256), dim3(256), rargs, 0, stream));
+        // the caller's stream; one slab per stream.  Second-pass groups run
+        // afterwards as persistent launches on the caller's stream.
+        HIP_TRY(c, hipLaunchKernel(kResetKernel, rgrid, rblock, rargs, 0, stream));
         HIP_TRY(c, hipEventRecord(c->fork, stream));
         for (int i = 0; i < kPlainStreams; ++i) HIP_TRY(c, hipStreamWaitEvent(c->plain[i], c->fork, 0));
         uint32_t idx = 0;
         for (auto &g : b->groups) {
+            if (g.pass) continue;
             int threads = 64 * (kTileWaves[g.waves] + 1);
             for (uint32_t j = 0; j < g.count; ++j, ++idx) {
                 int si = (int)(idx % kPlainStreams);
@@ -501,27 +556,35 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
                 a.slab_stride = 0;
                 a.results = d_res;
                 a.prof = b->d_prof;
+                a.hist = b->d_hist;
                 void *kargs[] = {&a};
-                HIP_TRY(c, hipLaunchKernel(persistent_kernel(g.waves, g.wide, g.sparse, g.census), dim3(1), dim3(threads), kargs,
-                                           g.lds, c->plain[si]));
+                HIP_TRY(c, hipLaunchKernel(persistent_kernel(g.waves, g.wide, g.sparse, g.census), dim3(1),
+                                           dim3(threads), kargs, g.lds, c->plain[si]));
             }
         }
         for (int i = 0; i < kPlainStreams; ++i) {
             HIP_TRY(c, hipEventRecord(c->join[i], c->plain[i]));
             HIP_TRY(c, hipStreamWaitEvent(stream, c->join[i], 0));
         }
+        for (size_t i = 0; i < args.size(); ++i) {
+            const Group &g = b->groups[i];
+            if (!g.pass) continue;
+            void *kargs[] = {&args[i]};
+            HIP_TRY(c, hipLaunchKernel(persistent_kernel(g.waves, g.wide, g.sparse, g.census), dim3(g.grid),
+                                       dim3(64 * (kTileWaves[g.waves] + 1)), kargs, g.lds, stream));
+        }
     } else {
-        // one graph: reset the queues, then every group's persistent launch
+        // one graph: reset the queues, every first-pass group's persistent
+        // launch side by side, then the second-pass groups after all of them
         std::string key;
         key.reserve(64 * args.size());
         for (size_t i = 0; i < args.size(); ++i) {
             const Group &g = b->groups[i];
             char buf[64];
-            std::snprintf(buf, sizeof(buf), "%d:%u:%u|", g.key, g.grid, g.lds);
+            std::snprintf(buf, sizeof(buf), "%d:%d:%u:%u|", g.pass, g.key, g.grid, g.lds);
             key += buf;
             key.append((const char *)&args[i], sizeof(KernelArgs));
         }
-        uint32_t nq = kKernelVariants * kNumWaveTiles;
         if (c->opt_graph) {
             hipGraphExec_t exec = cached_graph(c, key);
             if (!exec) {
@@ -530,24 +593,32 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
                 hipGraphNode_t reset;
                 hipKernelNodeParams rp;
                 std::memset(&rp, 0, sizeof(rp));
-                void *rargs[] = {&d_queue, &nq};
                 rp.func = (void *)kResetKernel;
-                rp.gridDim = dim3(1);
-                rp.blockDim = dim3(64);
+                rp.gridDim = rgrid;
+                rp.blockDim = rblock;
                 rp.kernelParams = rargs;
                 HIP_TRY(c, hipGraphAddKernelNode(&reset, graph, nullptr, 0, &rp));
-                for (size_t i = 0; i < args.size(); ++i) {
-                    const Group &g = b->groups[i];
-                    hipKernelNodeParams kp;
-                    std::memset(&kp, 0, sizeof(kp));
-                    void *kargs[] = {&args[i]};
-                    kp.func = (void *)persistent_kernel(g.waves, g.wide, g.sparse, g.census);
-                    kp.gridDim = dim3(g.grid);
-                    kp.blockDim = dim3(64 * (kTileWaves[g.waves] + 1));
-                    kp.sharedMemBytes = g.lds;
-                    kp.kernelParams = kargs;
-                    hipGraphNode_t node;
-                    HIP_TRY(c, hipGraphAddKernelNode(&node, graph, &reset, 1, &kp));
+                std::vector<hipGraphNode_t> first;
+                for (int pass = 0; pass < 2; ++pass) {
+                    for (size_t i = 0; i < args.size(); ++i) {
+                        const Group &g = b->groups[i];
+                        if (g.pass != pass) continue;
+                        hipKernelNodeParams kp;
+                        std::memset(&kp, 0, sizeof(kp));
+                        void *kargs[] = {&args[i]};
+                        kp.func = (void *)persistent_kernel(g.waves, g.wide, g.sparse, g.census);
+                        kp.gridDim = dim3(g.grid);
+                        kp.blockDim = dim3(64 * (kTileWaves[g.waves] + 1));
+                        kp.sharedMemBytes = g.lds;
+                        kp.kernelParams = kargs;
+                        hipGraphNode_t node;
+                        if (pass == 0) {
+                            HIP_TRY(c, hipGraphAddKernelNode(&node, graph, &reset, 1, &kp));
+                            first.push_back(node);
+                        } else {
+                            HIP_TRY(c, hipGraphAddKernelNode(&node, graph, first.data(), first.size(), &kp));
+                        }
+                    }
                 }
                 hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
@@ -560,13 +631,16 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
             }
             HIP_TRY(c, hipGraphLaunch(exec, stream));
         } else {
-            void *rargs[] = {&d_queue, &nq};
-            HIP_TRY(c, hipLaunchKernel(kResetKernel, dim3(1), dim3(64), rargs, 0, stream));
-            for (size_t i = 0; i < args.size(); ++i) {
-                const Group &g = b->groups[i];
-                void *kargs[] = {&args[i]};
-                HIP_TRY(c, hipLaunchKernel(persistent_kernel(g.waves, g.wide, g.sparse, g.census), dim3(g.grid),
-                                           dim3(64 * (kTileWaves[g.waves] + 1)), kargs, g.lds, stream));
+            HIP_TRY(c, hipLaunchKernel(kResetKernel, rgrid, rblock, rargs, 0, stream));
+            for (int pass = 0; pass < 2; ++pass) {
+                for (size_t i = 0; i < args.size(); ++i) {
+                    const Group &g = b->groups[i];
+                    if (g.pass != pass) continue;
+                    void *kargs[] = {&args[i]};
+                    HIP_TRY(c, hipLaunchKernel(persistent_kernel(g.waves, g.wide, g.sparse, g.census),
+                                               dim3(g.grid), dim3(64 * (kTileWaves[g.waves] + 1)), kargs,
+                                               g.lds, stream));
+                }
             }
         }
     }
@@ -630,6 +704,21 @@ int rsa_batch_profile(rsa_ctx *c, uint64_t batch_id, uint64_t *out, uint32_t n, 
     hipError_t e = hipEventSynchronize(b->ev_end);
     if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
     e = hipMemcpy(out, b->d_prof, (size_t)n * kProfSlots * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy");
+    return RSA_OK;
+}
+
+int rsa_batch_cluster_sizes(rsa_ctx *c, uint64_t batch_id, uint64_t *out, uint32_t n)
+{
+    if (!c) return RSA_EINVAL;
+    auto it = c->batches.find(batch_id);
+    if (it == c->batches.end()) return fail(c, RSA_ENOTFOUND, "unknown batch id");
+    Batch *b = it->second;
+    if (!b->d_hist) return fail(c, RSA_EINVAL, "no sample of the batch asked for cluster sizes");
+    if (n != b->n || (n > 0 && !out)) return fail(c, RSA_EINVAL, "count differs from batch size");
+    hipError_t e = hipEventSynchronize(b->ev_end);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    e = hipMemcpy(out, b->d_hist, (size_t)n * kSizeBins * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy");
     return RSA_OK;
 }

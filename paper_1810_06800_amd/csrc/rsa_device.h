@@ -138,6 +138,11 @@ constexpr int32_t kStatusNotRun = 2;
 // Descriptor flag of a time-sliced launch, above the public flags: the
 // sample has no saved state yet.
 constexpr uint32_t kDescFresh = 1u << 8;
+// Descriptor flag of a batch's second pass: rerun the sample up to its first
+// wrap (the first pass's n_wrap_any) and histogram the cluster sizes there.
+constexpr uint32_t kDescSizesPass = 1u << 9;
+// Cluster-size histogram bins: bin b counts clusters of 2^b .. 2^(b+1)-1 sites.
+constexpr uint32_t kSizeBins = 32;
 
 // What a sample that yields before jamming keeps in its slab.  The bitmaps,
 // map and union-find stay where they are; this record and the LDS row counts
@@ -194,6 +199,7 @@ struct KernelArgs {
     unsigned long long *prof;   // kProfSlots counters per sample, or null
     uint64_t quantum;           // wall-clock ticks a workgroup runs before its
                                 // sample yields; 0 = every sample to jamming
+    unsigned long long *hist;   // kSizeBins per sample (by result index), or null
 };
 
 // Optional per-sample phase counters (device wall-clock ticks unless noted).

@@ -173,7 +173,7 @@ struct Hdr {
     uint32_t resumed;        // state restored from the slab
     uint32_t preempt;        // the selecting wave stopped at its deadline
     uint32_t lab_stop;       // labelling ended early (both wrap steps known)
-    uint32_t pad2;
+    uint32_t stop;           // selection ends before this step (0 = at jamming)
     unsigned long long ncon[3];   // contact census: both H, both V, perpendicular
 };
 
@@ -778,7 +778,7 @@ struct TileCap {
 // deadline: wall-clock tick at which the run yields (0 = run to jamming); it
 // is checked every 16 steps, at a step whose placement is selected but not
 // yet deposited, so the saved state resumes exactly there.
-template <int NSEL, int ROWW, bool SPARSE>
+template <int NSEL, int ROWW, bool SPARSE, bool STOP>
 __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
 {
     constexpr int CAP = TileCap<NSEL>::value;
@@ -789,6 +789,8 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
     __builtin_amdgcn_s_setprio(2);   // latency-critical chain first on a shared SIMD
     const uint32_t L = c.L, k = c.k;
     const uint32_t t_begin = c.h->t0;
+    // with STOP, selection ends before step h->stop as if the lattice jammed there
+    const uint32_t stop_at = STOP && c.h->stop ? c.h->stop : 0xFFFFFFFFu;
     uint64_t occ = 0, seqh = c.h->seqh;
     uint32_t wchg = 0;
     const bool prof = c.prof != nullptr;
@@ -813,6 +815,7 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
     }
     while (alive) {
         // ---- step t: P is known.
+        if (STOP && t == stop_at) break;
         if (deadline && (t & 15) == 0 && t != t_begin && tick() >= deadline) {
             yielded = true;
             break;
@@ -1484,6 +1487,46 @@ __device__ __forceinline__ void contact_census(const Ctx &c, uint32_t tid)
 }
 
 // ---------------------------------------------------------------------------
+// Cluster sizes (Eq. 11)
+// ---------------------------------------------------------------------------
+
+// Histogram of the cluster sizes of k-mers 0 .. nk-1 (the whole lattice after
+// deposit nk): member counts per root in the k-mer record array (no longer
+// needed once labelling is done), then per root the bin of its size in
+// sites, 2^b <= size < 2^(b+1).  Writes kSizeBins counters to out.
+template <uint32_t NT>
+__device__ __forceinline__ void size_histogram(const Ctx &c, uint32_t tid, uint32_t nk,
+                                               unsigned long long *out)
+{
+    uint32_t *members = c.kmer;
+    unsigned long long *bins = (unsigned long long *)c.h_key;   // LDS, free after labelling
+    for (uint32_t i = tid; i < nk; i += NT) members[i] = 0;
+    if (tid < kSizeBins) bins[tid] = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    for (uint32_t i = tid; i < nk; i += NT) {
+        uint32_t root, meta;
+        int32_t dx, dy;
+        if (global_find(c, i, root, dx, dy, meta) && root < nk)
+            atomicAdd(&members[root], 1u);
+        else
+            bad = 1;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < nk; i += NT) {
+        // the counts were formed by atomics in L2: read them there too
+        const uint32_t m = __hip_atomic_load(&members[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (m) {
+            const uint64_t sites = (uint64_t)m * c.k;
+            atomicAdd(&bins[63 - __clzll((long long)sites)], 1ull);
+        }
+    }
+    if (bad) atomicOr(&c.h->nonwrap, 0x80000000u);   // marks a broken forest
+    __syncthreads();
+    if (tid < kSizeBins) out[tid] = (c.h->nonwrap & 0x80000000u) ? ~0ull : bins[tid];
+}
+
+// ---------------------------------------------------------------------------
 // One sample, then the persistent loop
 // ---------------------------------------------------------------------------
 
@@ -1570,8 +1613,20 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
     const bool track = (c.flags & 2u) != 0;
     // the contact census is compiled only into the CENSUS kernels, so that
     // the others keep their register allocation
-    const bool contacts = CENSUS && (c.flags & 4u) != 0;
+    const bool sizes_pass = CENSUS && (d.flags & kDescSizesPass) != 0;
+    const bool contacts = CENSUS && !sizes_pass && (c.flags & 4u) != 0;
     const bool sliced = deadline != 0;
+    uint32_t stop = 0;
+    if (sizes_pass) {
+        // second pass: stop right after the first wrap the first pass found
+        const int64_t nany = a.results[d.out].n_wrap_any;
+        if (nany <= 0 || a.results[d.out].status != 0) {
+            if (tid < kSizeBins) a.hist[(size_t)d.out * kSizeBins + tid] = nany <= 0 ? 0ull : ~0ull;
+            __syncthreads();
+            return;
+        }
+        stop = (uint32_t)nany;
+    }
     SampleState *st = (SampleState *)(slab + slab_layout(d.L, d.k).state);
     uint32_t *saved_cnt = (uint32_t *)((uint8_t *)st + kStateBytes);
     const uint32_t phase = sliced ? st->phase : 0u;
@@ -1609,6 +1664,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             h->resumed = 1;
             h->preempt = 0;
             h->lab_stop = st->lab_stop;
+            h->stop = 0;
             h->ncon[0] = h->ncon[1] = h->ncon[2] = 0;
         }
     } else {
@@ -1681,6 +1737,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             h->resumed = 0;
             h->preempt = 0;
             h->lab_stop = 0;
+            h->stop = stop;
             h->ncon[0] = h->ncon[1] = h->ncon[2] = 0;
         }
     }
@@ -1689,12 +1746,26 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
 
     // ---- the two chains
     if (wave == 0)
-        selector<NSEL, ROWW, SPARSE>(c, deadline);
+        selector<NSEL, ROWW, SPARSE, CENSUS>(c, deadline);
     else if (wave < (uint32_t)NSEL)
         helper<NSEL, SPARSE>(c, wave);
     else
-        labeler<(NSEL >= 7 ? 16 : 8)>(c, track || contacts);
+        labeler<(NSEL >= 7 ? 16 : 8)>(c, track || contacts || sizes_pass);
     __syncthreads();
+
+    if constexpr (CENSUS) {
+        if (sizes_pass) {
+            // ---- cluster-size histogram right after deposit `stop`; the
+            // first pass's result stands
+            if (c.h->status == 0 && c.h->sel_done == stop + 1) {
+                size_histogram<NT>(c, tid, stop, a.hist + (size_t)d.out * kSizeBins);
+            } else if (tid < kSizeBins) {
+                a.hist[(size_t)d.out * kSizeBins + tid] = ~0ull;
+            }
+            __syncthreads();
+            return;
+        }
+    }
 
     if (c.h->preempt && c.h->status == 0) {
         // ---- yield: save what the next run needs

@@ -49,6 +49,7 @@ constexpr int kPlainStreams = 4;
 
 struct Group {
     int key;                 // kernel_key of the instantiation
+    int pass;                // 0 = the runs, 1 = reruns for cluster sizes
     int waves;               // index into kTileWaves
     int wide;                // rows of more than 64 words (L > 4096)
     int sparse;              // clear mode
@@ -75,6 +76,7 @@ struct Batch {
     std::vector<Group> groups;
     int mode = RSA_MODE_BATCHED;
     unsigned long long *d_prof = nullptr;   // inside mem, or null
+    unsigned long long *d_hist = nullptr;   // cluster-size histograms, inside mem, or null
 };
 
 struct GraphEntry {

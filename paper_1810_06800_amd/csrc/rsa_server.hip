@@ -392,6 +392,8 @@ int rsa_server_submit(rsa_server *v, const rsa_sample_t *s, uint32_t n, uint64_t
     for (uint32_t i = 0; i < n; ++i) {
         if (!valid_sample(s[i]))
             return fail(c, RSA_EINVAL, "invalid descriptor at index " + std::to_string(i));
+        if (s[i].flags & RSA_FLAG_CLUSTER_SIZES)
+            return fail(c, RSA_EINVAL, "cluster sizes are a batch feature (rsa_batch_cluster_sizes)");
         if (lds_bytes(s[i].L) + 64 > c->lds_max) return fail(c, RSA_EINVAL, "lattice too large for LDS");
         if (Arena::round(slab_layout(s[i].L, s[i].k).total) > v->arena.size())
             return fail(c, RSA_ENOMEM, "sample larger than the server arena");

@@ -22,6 +22,8 @@ RSA_OK, RSA_EINVAL, RSA_ENOMEM, RSA_EDEVICE, RSA_ENOTREADY, RSA_EBUSY, RSA_ENOTF
 FLAG_H_ONLY = 1
 FLAG_TRACK_CLUSTERS = 2
 FLAG_CONTACTS = 4
+FLAG_CLUSTER_SIZES = 8
+SIZE_BINS = 32
 OPT_MODE, OPT_TILE, OPT_GRAPH, OPT_SLOTS, OPT_PROFILE = 1, 2, 3, 4, 5
 PROFILE_SLOTS = ("init", "sel_total", "sel_ring", "sel_select", "sel_clear", "lab_total", "lab_idle",
                  "lab_map", "lab_gather", "lab_resolve", "lab_merge", "lab_writeback",
@@ -31,10 +33,11 @@ MODE_BATCHED, MODE_PLAIN = 0, 1
 
 # Symbols declared in include/rsa.h.
 EXPORTS = ("rsa_create", "rsa_footprint_bytes", "rsa_run_batch", "rsa_results",
-           "rsa_batch_elapsed_ms", "rsa_batch_profile", "rsa_destroy", "rsa_strerror", "rsa_last_error",
-           "rsa_set_option", "rsa_get_option", "rsa_num_tiles", "rsa_tile_for_shape",
-           "rsa_tile_shape", "rsa_set_tile_table", "rsa_tile_for_sample", "rsa_server_create", "rsa_server_submit", "rsa_server_step",
-           "rsa_server_completed", "rsa_server_results", "rsa_server_stats", "rsa_server_destroy")
+           "rsa_batch_elapsed_ms", "rsa_batch_profile", "rsa_batch_cluster_sizes", "rsa_destroy",
+           "rsa_strerror", "rsa_last_error", "rsa_set_option", "rsa_get_option", "rsa_num_tiles",
+           "rsa_tile_for_shape", "rsa_tile_shape", "rsa_set_tile_table", "rsa_tile_for_sample",
+           "rsa_server_create", "rsa_server_submit", "rsa_server_step", "rsa_server_completed",
+           "rsa_server_results", "rsa_server_stats", "rsa_server_destroy")
 
 
 class Sample(ctypes.Structure):
@@ -107,6 +110,8 @@ def lib() -> ctypes.CDLL:
     L.rsa_batch_profile.argtypes = [vp, u64, ctypes.POINTER(u64), u32, ctypes.POINTER(u32),
                                     ctypes.POINTER(u32)]
     L.rsa_batch_profile.restype = i32
+    L.rsa_batch_cluster_sizes.argtypes = [vp, u64, ctypes.POINTER(u64), u32]
+    L.rsa_batch_cluster_sizes.restype = i32
     L.rsa_destroy.argtypes = [vp]
     L.rsa_destroy.restype = None
     L.rsa_strerror.argtypes = [i32]
@@ -306,6 +311,17 @@ class Context:
         m = slots.value
         assert m == len(PROFILE_SLOTS)
         return [dict(zip(PROFILE_SLOTS, out[i * m:(i + 1) * m])) for i in range(n)], khz.value
+
+    def cluster_sizes(self, batch):
+        """Cluster-size histograms of a batch (RSA_FLAG_CLUSTER_SIZES): one
+        list of SIZE_BINS counts per sample, bin b = clusters of 2^b .. 2^(b+1)-1
+        sites right after deposit n_wrap_any.  Call before results()."""
+        bid, n = batch
+        out = (ctypes.c_uint64 * (max(n, 1) * SIZE_BINS))()
+        rc = self._lib.rsa_batch_cluster_sizes(self._h, bid, out, n)
+        if rc != RSA_OK:
+            raise RsaError(rc, self.last_error())
+        return [list(out[i * SIZE_BINS:(i + 1) * SIZE_BINS]) for i in range(n)]
 
     def results(self, batch, wait: bool = True):
         """Results of a batch as a list of dicts (None if not ready and

@@ -163,7 +163,7 @@ def test_invalid_requests_rejected(ctx):
     from paper_1810_06800_amd import rsa
 
     with rsa.Server(ctx, arena_bytes=1 << 26) as srv:
-        for bad in [[(4, 5, 0, 0, 0)], [(16, 4, 0, 0, 16)], []]:
+        for bad in [[(4, 5, 0, 0, 0)], [(16, 4, 0, 0, 32)], [(16, 4, 0, 0, 8)], []]:
             with pytest.raises(rsa.RsaError) as e:
                 srv.submit(bad)
             assert e.value.code == rsa.RSA_EINVAL
