@@ -1,0 +1,47 @@
+"""GPU: the finite-size study on the batched engine (k = 1, 2, 4, 8 at
+L/k = 32 and 64, 64 runs per cell) against Table I.
+
+Table I is measured at L = 100k with single runs, so the comparison is
+statistical and loose: the jamming coverage at L/k = 64 within 0.003 (its
+finite-size shift is O(1/L), Eq. 10), and p_c extrapolated with Eq. 9 within
+0.02.  The runs are seeded, so the numbers are the same on every machine.
+"""
+import os
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_pc_pj.txt")
+
+
+def table1():
+    out = {}
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                n, pc, pj = line.split()
+                out[2 ** int(n)] = (float(pc), float(pj))
+    return out
+
+
+def test_thresholds_against_table_one():
+    import torch
+
+    from paper_1810_06800_amd import finite_size as fs
+    from paper_1810_06800_amd import rsa
+
+    assert torch.cuda.is_available()
+    ctx = rsa.Context(0)
+    try:
+        rows = fs.run_grid(ctx, [1, 2, 4, 8], [32, 64], 64, log=lambda m: print(m, flush=True))
+    finally:
+        ctx.close()
+    fits = fs.fits(rows)
+    paper = table1()
+    for k in (1, 2, 4, 8):
+        pc_paper, pj_paper = paper[k]
+        big = max((r for r in rows if r["k"] == k), key=lambda r: r["L"])
+        assert abs(big["pj"] - pj_paper) <= 0.003, (k, big["pj"], pj_paper)
+        assert abs(fits[k]["pc_inf"]["value"] - pc_paper) <= 0.02, (k, fits[k]["pc_inf"], pc_paper)
+        assert big["deposits_per_s"] > 0
