@@ -41,6 +41,8 @@ namespace rsa {
 constexpr int32_t kErrSelect = -100;
 constexpr int32_t kErrLabel = -101;
 constexpr uint32_t kMaxHops = 64;   // union by rank keeps trees below log2(L^2) levels
+constexpr uint32_t kSideGather = 512;   // k from which contacts are gathered side by side
+                                        // (sparse-clear kernels)
 
 // ---------------------------------------------------------------------------
 // Small device helpers
@@ -108,6 +110,18 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ uint32_t first_lane(uint64_t ballot) { return (uint32_t)(__ffsll((long long)ballot) - 1); }
+
+// Set bits of `ballot` below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t ballot)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
+}
+
+// The previous lane's v (DPP wave shift right by one); lane 0 gets `first`.
+__device__ __forceinline__ int32_t from_previous_lane(int32_t v, int32_t first)
+{
+    return __builtin_amdgcn_update_dpp(first, v, 0x138, 0xf, 0xf, false);
+}
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, key bumped by
 // the Weyl constants between rounds.  Only output words 0 and 1 are used.
@@ -1266,7 +1280,7 @@ __device__ __forceinline__ void process_chunk(const Ctx &c, LabelState &ls, uint
     if (prof) prof_add(c, kProfLabMerge, tick() - p0);
 }
 
-template <int G>
+template <int G, bool SIDE>
 __device__ __forceinline__ void labeler(Ctx &c, bool track)
 {
     const uint32_t lane = lane_id();
@@ -1355,7 +1369,79 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track)
         const uint32_t total = B * nC;
         const bool dedupe = k != L;
         bool stop = false;
-        for (uint32_t g0 = 0; g0 < total && !stop; g0 += 64 * G) {
+        const bool side_gather = SIDE && k >= kSideGather;
+        if (side_gather) {
+            // Long k-mers: deposit by deposit, side by side.  A side's
+            // contacts lie on one lattice line (the row above / below an H
+            // k-mer, the column left / right of a V one), so lane j's site
+            // is j steps along it; the two ends follow as a short third side.
+            // Fewer instructions per contact, but one flight of reads per
+            // side: it pays once a side is several flights long.
+            for (uint32_t i = 0; i < B && !stop; ++i) {
+                const uint32_t m = tl + i;
+                const uint32_t a = uniform(lds_peek(&c.banc[i]));
+                const uint32_t om = a >> 31, site = a & 0x7FFFFFFFu;
+                const uint32_t ay = fdiv(site, c.fL), ax = site - ay * L;
+                const uint32_t along0 = om ? ay : ax;   // coordinate along the k-mer
+                const uint32_t across = om ? ax : ay;   // the other one
+                for (uint32_t side = 0; side < 3 && !stop; ++side) {
+                    const uint32_t len = side < 2 ? k : 2u;
+                    const uint32_t fix = side == 0 ? (across == 0 ? L - 1 : across - 1)
+                                                   : (across + 1 == L ? 0u : across + 1);
+                    cn = -1;
+                    for (uint32_t j0 = 0; j0 < len && !stop; j0 += 64 * G) {
+                        int32_t nval[G];
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            const uint32_t j = j0 + 64 * g + lane;
+                            int32_t v = -1;
+                            if (j < len) {
+                                // sides: along0 + j; ends: one before site 0, one after site k-1
+                                uint32_t al = side < 2 ? along0 + j : (j == 0 ? along0 + L - 1 : along0 + k);
+                                al = al >= L ? al - L : al;
+                                const uint32_t cr = side < 2 ? fix : across;
+                                v = c.map[om ? map_index(c, al, cr) : map_index(c, cr, al)];
+                            }
+                            nval[g] = v;
+                        }
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            const uint32_t jr = j0 + 64 * g;
+                            if (jr >= len || stop) continue;
+                            const uint32_t j = jr + lane;
+                            const int32_t n = nval[g];
+                            const bool keep = j < len && n >= 0 && (uint32_t)n <= m;
+                            const int32_t key = keep ? n : -1;
+                            const int32_t pn = from_previous_lane(key, cn);
+                            const bool emit = keep && !(dedupe && side < 2 && j > 0 && pn == n);
+                            cn = (int32_t)bcast((uint32_t)key, 63);
+                            const uint64_t bal = __ballot(emit);
+                            if (emit) {
+                                const uint32_t idx = ne + lanes_below(bal);
+                                c.e_step[idx] = m;
+                                c.e_ms[idx] = (uint32_t)n;
+                                c.e_vx[idx] = (int32_t)(side < 2 ? side * k + j : 2 * k + j);
+                            }
+                            ne += (uint32_t)__popcll(bal);
+                            __builtin_amdgcn_wave_barrier();
+                            const bool last = i + 1 == B && side == 2 && jr + 64 >= len;
+                            if (ne + 64 > kEdges || last) {
+                                if (prof) {
+                                    p_gather += tick() - p0;
+                                    p_edges += ne;
+                                }
+                                process_chunk(c, ls, ne);
+                                if (prof) p0 = tick();
+                                ne = 0;
+                                if (!track && ls.nx >= 0 && ls.ny >= 0) stop = true;
+                                if (c.h->status != 0) stop = true;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        for (uint32_t g0 = 0; !side_gather && g0 < total && !stop; g0 += 64 * G) {
             int32_t nval[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -1750,7 +1836,9 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
     else if (wave < (uint32_t)NSEL)
         helper<NSEL, SPARSE>(c, wave);
     else
-        labeler<(NSEL >= 7 ? 16 : 8)>(c, track || contacts || sizes_pass);
+        // the side-by-side gather is compiled into the sparse-clear kernels
+        // only (long k-mers); it would raise the others' register count
+        labeler<(NSEL >= 7 && !CENSUS ? 16 : 8), SPARSE>(c, track || contacts || sizes_pass);
     __syncthreads();
 
     if constexpr (CENSUS) {
