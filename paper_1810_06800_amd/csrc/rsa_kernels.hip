@@ -189,35 +189,57 @@ struct Hdr {
     uint32_t lab_stop;       // labelling ended early (both wrap steps known)
     uint32_t stop;           // selection ends before this step (0 = at jamming)
     unsigned long long ncon[3];   // contact census: both H, both V, perpendicular
+    unsigned long long sel_acc[7];   // selecting wave's phase counters (profiling)
 };
+
+// Selecting-wave profile accumulators, kept in LDS rather than in registers.
+enum SelAcc { kAccStart = 0, kAccRing, kAccSelect, kAccClear, kAccHook, kAccProcess, kAccSpec };
 
 struct Ctx {
     unsigned long long *prof;   // this sample's counters, or null
-    uint32_t L, k, wd, flags, sample, L2;
-    uint32_t ncap;     // k-mer records in the slab, L*L/k + 1
+    uint32_t L, k, wd, flags, sample;
     uint32_t k0, k1;   // Philox key
-    // bitmap tiles: 2^lg_tr rows x 2^lg_tw words, tpr tiles per padded row
-    uint32_t lg_tr, lg_tw, tr_m, tw_m, tpr, wp;
-    // site-map tiles: 2^lg_mr rows x 2^lg_mc sites, mtpr tiles per padded row
-    uint32_t lg_mr, lg_mc, mr_m, mc_m, mtpr, lp;
+    // bitmap tiles: 2^lg_tr rows x 2^(4-lg_tr) words; site-map tiles:
+    // 2^lg_mr rows x 2^(5-lg_mr) sites (the rest is derived on use, which
+    // keeps the scalar registers of the selecting wave free)
+    uint32_t lg_tr, lg_mr;
     uint32_t spec_rows;
     FastDiv fL, fk, fC, fwd, fwp;
     uint64_t *av0, *av1;   // availability bitmaps of H / V placements
     uint64_t *sm0, *sm1;   // their summary bits (sparse clear only)
-    uint32_t swp;          // summary words per row
-    uint32_t sparse;
     int32_t *map;
     int4 *node;
     uint32_t *kmer;
     Hdr *h;
     uint32_t *cnt0, *cnt1, *cnt2;
-    uint32_t n1, n2;
     uint32_t *ring, *banc;
-    uint32_t *e_step, *e_ms;
-    int32_t *e_vx, *e_vy;
-    uint32_t *s_par, *s_meta, *s_gid;
-    int32_t *s_dx, *s_dy;
-    uint32_t *h_key, *h_val;
+    uint32_t *e_step;   // edge lists: step, then ms, vx, vy (kEdges each)
+    uint32_t *s_par;    // local union-find: parent, then meta, gid, dx, dy (kSlots each)
+    uint32_t *h_key;    // root hash: keys, then values (kHash each)
+
+    __device__ __forceinline__ uint32_t L2() const { return L * L; }
+    __device__ __forceinline__ uint32_t ncap() const { return L * L / k + 1; }
+    __device__ __forceinline__ uint32_t wp() const { return padded_words(L); }
+    __device__ __forceinline__ uint32_t lp() const { return padded_side(L); }
+    __device__ __forceinline__ uint32_t swp() const { return summary_words(L); }
+    __device__ __forceinline__ uint32_t n1() const { return (2 * L + 63) / 64; }
+    __device__ __forceinline__ uint32_t n2() const { return (2 * L + 4095) / 4096; }
+    __device__ __forceinline__ uint32_t lg_tw() const { return 4 - lg_tr; }
+    __device__ __forceinline__ uint32_t tr_m() const { return (1u << lg_tr) - 1; }
+    __device__ __forceinline__ uint32_t tw_m() const { return (1u << (4 - lg_tr)) - 1; }
+    __device__ __forceinline__ uint32_t tpr() const { return padded_words(L) >> (4 - lg_tr); }
+    __device__ __forceinline__ uint32_t lg_mc() const { return 5 - lg_mr; }
+    __device__ __forceinline__ uint32_t mr_m() const { return (1u << lg_mr) - 1; }
+    __device__ __forceinline__ uint32_t mc_m() const { return (1u << (5 - lg_mr)) - 1; }
+    __device__ __forceinline__ uint32_t mtpr() const { return padded_side(L) >> (5 - lg_mr); }
+    __device__ __forceinline__ uint32_t *e_ms() const { return e_step + kEdges; }
+    __device__ __forceinline__ int32_t *e_vx() const { return (int32_t *)(e_step + 2 * kEdges); }
+    __device__ __forceinline__ int32_t *e_vy() const { return (int32_t *)(e_step + 3 * kEdges); }
+    __device__ __forceinline__ uint32_t *s_meta() const { return s_par + kSlots; }
+    __device__ __forceinline__ uint32_t *s_gid() const { return s_par + 2 * kSlots; }
+    __device__ __forceinline__ int32_t *s_dx() const { return (int32_t *)(s_par + 3 * kSlots); }
+    __device__ __forceinline__ int32_t *s_dy() const { return (int32_t *)(s_par + 4 * kSlots); }
+    __device__ __forceinline__ uint32_t *h_val() const { return h_key + kHash; }
 };
 
 __device__ __forceinline__ uint64_t *bitmap(const Ctx &c, uint32_t o) { return o ? c.av1 : c.av0; }
@@ -225,15 +247,15 @@ __device__ __forceinline__ uint64_t *bitmap(const Ctx &c, uint32_t o) { return o
 // Word w of bitmap row `row` inside its 128-byte tile.
 __device__ __forceinline__ size_t bm_index(const Ctx &c, uint32_t row, uint32_t w)
 {
-    return (((size_t)(row >> c.lg_tr) * c.tpr + (w >> c.lg_tw)) << 4) + ((row & c.tr_m) << c.lg_tw) +
-           (w & c.tw_m);
+    return (((size_t)(row >> c.lg_tr) * c.tpr() + (w >> c.lg_tw())) << 4) + ((row & c.tr_m()) << c.lg_tw()) +
+           (w & c.tw_m());
 }
 
 // Site (y, x) of the map inside its 128-byte tile.
 __device__ __forceinline__ size_t map_index(const Ctx &c, uint32_t y, uint32_t x)
 {
-    return (((size_t)(y >> c.lg_mr) * c.mtpr + (x >> c.lg_mc)) << 5) + ((y & c.mr_m) << c.lg_mc) +
-           (x & c.mc_m);
+    return (((size_t)(y >> c.lg_mr) * c.mtpr() + (x >> c.lg_mc())) << 5) + ((y & c.mr_m()) << c.lg_mc()) +
+           (x & c.mc_m());
 }
 
 __device__ __forceinline__ uint64_t tick() { return (uint64_t)wall_clock64(); }
@@ -366,7 +388,7 @@ __device__ __forceinline__ RectLane rect_lane(const Ctx &c, const Rect &r, uint3
         const uint32_t wsub = lane & ((1u << r.lg) - 1);
         rl.w = wsub < r.nA ? r.a0 + wsub : wsub - r.nA;
         rl.mask = wsub < r.nw ? col_mask(c.L, r.c0, r.len, rl.w) : 0;
-        rl.colpart = ((rl.w >> c.lg_tw) << 4) + (rl.w & c.tw_m);
+        rl.colpart = ((rl.w >> c.lg_tw()) << 4) + (rl.w & c.tw_m());
         const uint32_t all = (r.nrows + rl.rows_per - 1) / rl.rows_per;   // row groups
         rl.rounds = all > wv ? (all - wv + nwv - 1) / nwv : 0;
         rl.nchunk = 0;
@@ -394,7 +416,7 @@ __device__ __forceinline__ bool rect_round(const Ctx &c, const Rect &r, const Re
         if (i >= r.nrows || mask == 0) return false;
         row = r.row0 + i;
         row = row >= c.L ? row - c.L : row;
-        at = ((size_t)(row >> c.lg_tr) * c.tpr << 4) + ((row & c.tr_m) << c.lg_tw) + rl.colpart;
+        at = ((size_t)(row >> c.lg_tr) * c.tpr() << 4) + ((row & c.tr_m()) << c.lg_tw()) + rl.colpart;
         return true;
     }
     i = g / rl.nchunk;
@@ -515,7 +537,7 @@ __device__ __forceinline__ void sparse_rect(const Ctx &c, const Rect &r, uint32_
         }
 #pragma unroll
         for (int s = 0; s < CAP; ++s)
-            if (cand[s]) cand[s] &= sm[(size_t)srow[s] * c.swp + ssw[s]];
+            if (cand[s]) cand[s] &= sm[(size_t)srow[s] * c.swp() + ssw[s]];
         // data words, DCAP per lane per round
         for (;;) {
             bool any = false;
@@ -566,7 +588,7 @@ __device__ __forceinline__ void sparse_rect(const Ctx &c, const Rect &r, uint32_
         }
 #pragma unroll
         for (int s = 0; s < CAP; ++s)
-            if (zero[s]) atomicAnd((unsigned long long *)&sm[(size_t)srow[s] * c.swp + ssw[s]], ~zero[s]);
+            if (zero[s]) atomicAnd((unsigned long long *)&sm[(size_t)srow[s] * c.swp() + ssw[s]], ~zero[s]);
     }
 }
 
@@ -635,14 +657,14 @@ __device__ __forceinline__ bool locate_row(const Ctx &c, uint32_t inc2, uint32_t
 {
     const uint32_t lane = lane_id();
     uint32_t g = 0;
-    if (c.n2 > 1) {
+    if (c.n2() > 1) {
         uint64_t bal = __ballot(inc2 > r);
         if (bal == 0) return false;
         g = first_lane(bal);
         r -= bcast(inc2 - v2, g);
     }
     uint32_t i1 = g * 64 + lane;
-    uint32_t v = i1 < c.n1 ? lds_peek(&c.cnt1[i1]) : 0;
+    uint32_t v = i1 < c.n1() ? lds_peek(&c.cnt1[i1]) : 0;
     uint32_t inc = wave_scan(v);
     uint64_t bal = __ballot(inc > r);
     if (bal == 0) return false;
@@ -694,7 +716,7 @@ __device__ __forceinline__ bool pick_in_row(const Ctx &c, const RowWords<ROWW> &
     const uint32_t x = wsel * 64 + first_lane(bal);
     if (x >= c.L) return false;
     const uint32_t o = R >= c.L ? 1u : 0u;
-    P = uniform(o * c.L2 + (R - o * c.L) * c.L + x);
+    P = uniform(o * c.L2() + (R - o * c.L) * c.L + x);
     return true;
 }
 
@@ -702,12 +724,12 @@ __device__ __forceinline__ bool pick_in_row(const Ctx &c, const RowWords<ROWW> &
 __device__ __forceinline__ uint32_t scan_top(const Ctx &c, uint32_t &inc2, uint32_t &v2)
 {
     const uint32_t lane = lane_id();
-    if (c.n2 == 1) {   // one group: its sum is A, no scan needed
+    if (c.n2() == 1) {   // one group: its sum is A, no scan needed
         v2 = lds_peek(&c.cnt2[0]);
         inc2 = v2;
         return uniform(v2);
     }
-    v2 = lane < c.n2 ? lds_peek(&c.cnt2[lane]) : 0;
+    v2 = lane < c.n2() ? lds_peek(&c.cnt2[lane]) : 0;
     inc2 = wave_scan(v2);
     return bcast(inc2, 63);
 }
@@ -808,8 +830,9 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
     uint64_t occ = 0, seqh = c.h->seqh;
     uint32_t wchg = 0;
     const bool prof = c.prof != nullptr;
-    uint64_t p_start = prof ? tick() : 0, p_ring = 0, p_sel = 0, p_clr = 0, p0 = 0, spec_hits = 0;
-    uint64_t p_hook = 0, p_proc = 0;
+    unsigned long long *const acc = c.h->sel_acc;   // lane 0 adds to these when profiling
+    uint64_t p0 = 0;
+    if (prof && lane == 0) acc[kAccStart] = tick();
     // draws for the 64 steps of t_begin's block (lane = step within the block)
     uint64_t u_pre = philox_u64((t_begin & ~63u) + lane, c.sample, c.k0, c.k1);
     uint32_t t = t_begin;
@@ -836,7 +859,7 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         }
         // A correct run never deposits more than L*L/k k-mers; stop before
         // the k-mer records would overflow.
-        if (t + 1 >= c.ncap) {
+        if (t + 1 >= c.ncap()) {
             if (lane == 0) c.h->status = kErrSelect;
             break;
         }
@@ -844,15 +867,15 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
             if (prof) p0 = tick();
             while (!lds_load(&c.h->lab_exit) && t - lds_load(&c.h->lab_progress) >= kRing)
                 __builtin_amdgcn_s_sleep(2);
-            if (prof) p_ring += tick() - p0;
+            if (prof && lane == 0) acc[kAccRing] += tick() - p0;
         }
         if (prof) p0 = tick();
         if (lane == 0) {
             c.ring[t & (kRing - 1)] = P;
             lds_store(&c.h->sel_progress, t + 1);
         }
-        const uint32_t o = P >= c.L2 ? 1u : 0u;
-        const uint32_t rem = P - o * c.L2;
+        const uint32_t o = P >= c.L2() ? 1u : 0u;
+        const uint32_t rem = P - o * c.L2();
         const uint32_t y = fdiv(rem, c.fL), x = rem - y * L;
         seqh += mix64(((uint64_t)t << 32) | P);
         for (uint32_t i = lane; i < k; i += 64) {
@@ -886,14 +909,14 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         if constexpr (SPW > 0) read_ahead<SPW>(c, cl, u1, sp);
         if (prof) {
             uint64_t ph1 = tick();
-            p_hook += ph1 - ph;
+            if (lane == 0) acc[kAccHook] += ph1 - ph;
             ph = ph1;
         }
         if constexpr (SPARSE)
             sparse_clear<CAP>(c, cl, 0, NSEL, wchg);
         else
             clear_items<CAP>(c, cl, 0, NSEL, wchg);
-        if (prof) p_proc += tick() - ph;
+        if (prof && lane == 0) acc[kAccProcess] += tick() - ph;
         if (NSEL > 1) {
             // helpers' bitmap stores must be visible before the next select
             uint32_t want = t1 * (NSEL - 1);
@@ -902,7 +925,7 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         }
         if (prof) {
             uint64_t p1 = tick();
-            p_clr += p1 - p0;
+            if (lane == 0) acc[kAccClear] += p1 - p0;
             p0 = p1;
         }
         // ---- exact select for step t+1
@@ -919,7 +942,7 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         if (SPW > 0 && sp.nr && ro == sp.o && ry >= sp.y0 && ry < sp.y0 + sp.nr) {
             row_from_window<SPW == 0 ? 1 : SPW, ROWW>(c, sp, ry, rw);
             patch_row(c, cl, R, rw);
-            ++spec_hits;
+            if (prof && lane == 0) ++acc[kAccSpec];
         } else {
             load_row(c, R, rw);
         }
@@ -927,17 +950,17 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
             if (lane == 0) c.h->status = kErrSelect;
             break;
         }
-        if (prof) p_sel += tick() - p0;
+        if (prof && lane == 0) acc[kAccSelect] += tick() - p0;
     }
     if (prof) {
-        prof_add(c, kProfSelTotal, tick() - p_start);
-        prof_add(c, kProfSelRing, p_ring);
-        prof_add(c, kProfSelSelect, p_sel);
-        prof_add(c, kProfSelClear, p_clr);
+        prof_add(c, kProfSelTotal, tick() - acc[kAccStart]);
+        prof_add(c, kProfSelRing, acc[kAccRing]);
+        prof_add(c, kProfSelSelect, acc[kAccSelect]);
+        prof_add(c, kProfSelClear, acc[kAccClear]);
         prof_add(c, kProfSteps, t);
-        prof_add(c, kProfSpecHits, spec_hits);
-        prof_add(c, kProfSelHook, p_hook);
-        prof_add(c, kProfSelProcess, p_proc);
+        prof_add(c, kProfSpecHits, acc[kAccSpec]);
+        prof_add(c, kProfSelHook, acc[kAccHook]);
+        prof_add(c, kProfSelProcess, acc[kAccProcess]);
     }
     occ = wave_sum64(occ);
     uint32_t wsum = wave_sum32(wchg);
@@ -976,8 +999,8 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
         if (stop) break;
         g = gen;
         uint32_t P = uniform(lds_peek(&c.h->cur_p));
-        uint32_t o = P >= c.L2 ? 1u : 0u;
-        uint32_t rem = P - o * c.L2;
+        uint32_t o = P >= c.L2() ? 1u : 0u;
+        uint32_t rem = P - o * c.L2();
         uint32_t y = fdiv(rem, c.fL);
         uint32_t x = rem - y * c.L;
         const Clear cl = make_clear(c, o, y, x);
@@ -1010,7 +1033,7 @@ __device__ __forceinline__ bool global_find(const Ctx &c, uint32_t x, uint32_t &
             ok = true;
             break;
         }
-        if ((uint32_t)nd.x >= c.ncap) break;   // not a k-mer id: corrupted record
+        if ((uint32_t)nd.x >= c.ncap()) break;   // not a k-mer id: corrupted record
         ax += nd.y;
         ay += nd.z;
         cur = (uint32_t)nd.x;
@@ -1032,15 +1055,15 @@ __device__ __forceinline__ uint32_t local_find(const Ctx &c, uint32_t a, int32_t
         if (p == x) break;
         uint32_t gp = c.s_par[p];
         if (gp == p) {
-            ax += c.s_dx[x];
-            ay += c.s_dy[x];
+            ax += c.s_dx()[x];
+            ay += c.s_dy()[x];
             x = p;
             break;
         }
-        int32_t hx = c.s_dx[x] + c.s_dx[p], hy = c.s_dy[x] + c.s_dy[p];
+        int32_t hx = c.s_dx()[x] + c.s_dx()[p], hy = c.s_dy()[x] + c.s_dy()[p];
         c.s_par[x] = gp;
-        c.s_dx[x] = hx;
-        c.s_dy[x] = hy;
+        c.s_dx()[x] = hx;
+        c.s_dy()[x] = hy;
         ax += hx;
         ay += hy;
         x = gp;
@@ -1109,10 +1132,10 @@ __device__ __forceinline__ void reset_slots(const Ctx &c, const LabelState &ls)
     const uint32_t lane = lane_id();
     for (uint32_t s = lane; s < ls.nb; s += 64) {
         c.s_par[s] = s;
-        c.s_dx[s] = 0;
-        c.s_dy[s] = 0;
-        c.s_meta[s] = 0;
-        c.s_gid[s] = ls.base + s;
+        c.s_dx()[s] = 0;
+        c.s_dy()[s] = 0;
+        c.s_meta()[s] = 0;
+        c.s_gid()[s] = ls.base + s;
     }
     for (uint32_t i = lane; i < kHash; i += 64) c.h_key[i] = 0;
     if (lane == 0) c.h->nslots = ls.nb;
@@ -1127,15 +1150,15 @@ __device__ __forceinline__ void write_back(const Ctx &c)
         uint32_t x = s;
         int32_t dx = 0, dy = 0;
         for (uint32_t it = 0; it < kSlots && c.s_par[x] != x; ++it) {
-            dx += c.s_dx[x];
-            dy += c.s_dy[x];
+            dx += c.s_dx()[x];
+            dy += c.s_dy()[x];
             x = c.s_par[x];
         }
-        uint32_t g = c.s_gid[s];
+        uint32_t g = c.s_gid()[s];
         if (x == s)
-            c.node[g] = make_int4((int)g, 0, 0, (int)c.s_meta[s]);
+            c.node[g] = make_int4((int)g, 0, 0, (int)c.s_meta()[s]);
         else
-            c.node[g] = make_int4((int)c.s_gid[x], dx, dy, 0);
+            c.node[g] = make_int4((int)c.s_gid()[x], dx, dy, 0);
     }
 }
 
@@ -1177,16 +1200,16 @@ __device__ __forceinline__ uint32_t resolve_slot(const Ctx &c, const LabelState 
     if (won) {
         uint32_t s = atomicAdd(&c.h->nslots, 1u);
         c.s_par[s] = s;
-        c.s_dx[s] = 0;
-        c.s_dy[s] = 0;
-        c.s_meta[s] = meta;
-        c.s_gid[s] = root;
-        c.h_val[pos] = s;
+        c.s_dx()[s] = 0;
+        c.s_dy()[s] = 0;
+        c.s_meta()[s] = meta;
+        c.s_gid()[s] = root;
+        c.h_val()[pos] = s;
     }
     __builtin_amdgcn_wave_barrier();
     uint32_t slot = 0;
     if (local) slot = id - ls.base;
-    if (global) slot = c.h_val[pos];
+    if (global) slot = c.h_val()[pos];
     return slot;
 }
 
@@ -1214,7 +1237,7 @@ __device__ __forceinline__ void process_chunk(const Ctx &c, LabelState &ls, uint
         uint32_t e = e0 + lane;
         bool act = e < ne;
         uint32_t m = act ? c.e_step[e] : 0;
-        uint32_t n = act ? c.e_ms[e] : 0;
+        uint32_t n = act ? c.e_ms()[e] : 0;
         // the neighbour's anchor (read now, used after the finds)
         uint32_t an = 0;
         if (act) an = n >= ls.tl ? c.banc[n - ls.tl] : c.kmer[n];
@@ -1223,7 +1246,7 @@ __device__ __forceinline__ void process_chunk(const Ctx &c, LabelState &ls, uint
         uint32_t sn = resolve_slot(c, ls, act, n, dnx, dny);
         if (act) {
             // v = anchor_m - anchor_n through this contact, unwrapped
-            const Contact ct = contact_of(c, ls.tl, (m - ls.tl) * nC + (uint32_t)c.e_vx[e], 0xFFFFFFFFu);
+            const Contact ct = contact_of(c, ls.tl, (m - ls.tl) * nC + (uint32_t)c.e_vx()[e], 0xFFFFFFFFu);
             const uint32_t on = an >> 31, ns = an & 0x7FFFFFFFu;
             const uint32_t ny_ = fdiv(ns, c.fL), nx_ = ns - ny_ * L;
             int32_t j = on ? (int32_t)ct.by - (int32_t)ny_ : (int32_t)ct.bx - (int32_t)nx_;
@@ -1231,9 +1254,9 @@ __device__ __forceinline__ void process_chunk(const Ctx &c, LabelState &ls, uint
             const int32_t unx = on ? 0 : 1, uny = on ? 1 : 0;
             const int32_t vx = j * unx - ct.ii * ct.umx - ct.ex;
             const int32_t vy = j * uny - ct.ii * ct.umy - ct.ey;
-            c.e_ms[e] = sm | (sn << 16);
-            c.e_vx[e] = vx + dnx - dmx;
-            c.e_vy[e] = vy + dny - dmy;
+            c.e_ms()[e] = sm | (sn << 16);
+            c.e_vx()[e] = vx + dnx - dmx;
+            c.e_vy()[e] = vy + dny - dmy;
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -1245,30 +1268,30 @@ __device__ __forceinline__ void process_chunk(const Ctx &c, LabelState &ls, uint
     // merge in deposit order (every lane walks the same list)
     int32_t nx = ls.nx, ny = ls.ny;
     for (uint32_t e = 0; e < ne; ++e) {
-        uint32_t ms = c.e_ms[e];
-        int32_t vx = c.e_vx[e], vy = c.e_vy[e];
+        uint32_t ms = c.e_ms()[e];
+        int32_t vx = c.e_vx()[e], vy = c.e_vy()[e];
         int32_t dax, day, dbx, dby;
         uint32_t ra = local_find(c, ms & 0xFFFFu, dax, day);
         uint32_t rb = local_find(c, ms >> 16, dbx, dby);
         if (ra != rb) {
-            uint32_t ma = c.s_meta[ra], mb = c.s_meta[rb];
+            uint32_t ma = c.s_meta()[ra], mb = c.s_meta()[rb];
             if ((ma & 0xFFu) < (mb & 0xFFu)) {
                 c.s_par[ra] = rb;
-                c.s_dx[ra] = vx - dax + dbx;
-                c.s_dy[ra] = vy - day + dby;
-                c.s_meta[rb] = mb | (ma & 0x300u);
+                c.s_dx()[ra] = vx - dax + dbx;
+                c.s_dy()[ra] = vy - day + dby;
+                c.s_meta()[rb] = mb | (ma & 0x300u);
             } else {
                 c.s_par[rb] = ra;
-                c.s_dx[rb] = dax - dbx - vx;
-                c.s_dy[rb] = day - dby - vy;
+                c.s_dx()[rb] = dax - dbx - vx;
+                c.s_dy()[rb] = day - dby - vy;
                 uint32_t bump = (ma & 0xFFu) == (mb & 0xFFu) ? 1u : 0u;
-                c.s_meta[ra] = (ma | (mb & 0x300u)) + bump;
+                c.s_meta()[ra] = (ma | (mb & 0x300u)) + bump;
             }
         } else {
             int32_t wx = dax - dbx - vx, wy = day - dby - vy;
             if (wx != 0 || wy != 0) {
                 uint32_t step = c.e_step[e];
-                c.s_meta[ra] |= (wx != 0 ? 0x100u : 0u) | (wy != 0 ? 0x200u : 0u);
+                c.s_meta()[ra] |= (wx != 0 ? 0x100u : 0u) | (wy != 0 ? 0x200u : 0u);
                 if (wx != 0 && nx < 0) nx = (int32_t)step + 1;
                 if (wy != 0 && ny < 0) ny = (int32_t)step + 1;
             }
@@ -1321,8 +1344,8 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track)
         // take the placements out of the ring
         if (lane < B) {
             uint32_t P = c.ring[(tl + lane) & (kRing - 1)];
-            uint32_t o = P >= c.L2 ? 1u : 0u;
-            uint32_t a = (P - o * c.L2) | (o << 31);
+            uint32_t o = P >= c.L2() ? 1u : 0u;
+            uint32_t a = (P - o * c.L2()) | (o << 31);
             c.banc[lane] = a;
             c.kmer[tl + lane] = a;
         }
@@ -1419,8 +1442,8 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track)
                             if (emit) {
                                 const uint32_t idx = ne + lanes_below(bal);
                                 c.e_step[idx] = m;
-                                c.e_ms[idx] = (uint32_t)n;
-                                c.e_vx[idx] = (int32_t)(side < 2 ? side * k + j : 2 * k + j);
+                                c.e_ms()[idx] = (uint32_t)n;
+                                c.e_vx()[idx] = (int32_t)(side < 2 ? side * k + j : 2 * k + j);
                             }
                             ne += (uint32_t)__popcll(bal);
                             __builtin_amdgcn_wave_barrier();
@@ -1470,8 +1493,8 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track)
                 if (emit) {
                     uint32_t idx = ne + off;
                     c.e_step[idx] = m;
-                    c.e_ms[idx] = (uint32_t)n;
-                    c.e_vx[idx] = (int32_t)ci;
+                    c.e_ms()[idx] = (uint32_t)n;
+                    c.e_vx()[idx] = (int32_t)ci;
                 }
                 ne += (uint32_t)__popcll(bal);
                 __builtin_amdgcn_wave_barrier();
@@ -1530,9 +1553,9 @@ __device__ __forceinline__ void contact_census(const Ctx &c, uint32_t tid)
     const uint32_t L = c.L;
     const uint32_t groups = NT / 32;            // tiles per pass
     const uint32_t grp = tid >> 5, off = tid & 31;
-    const uint32_t oy = off >> c.lg_mc, ox = off & c.mc_m;
-    const uint32_t ntr = c.lp >> c.lg_mr;       // tile rows
-    const uint32_t ntiles = ntr * c.mtpr;
+    const uint32_t oy = off >> c.lg_mc(), ox = off & c.mc_m();
+    const uint32_t ntr = c.lp() >> c.lg_mr;       // tile rows
+    const uint32_t ntiles = ntr * c.mtpr();
     uint32_t n[3] = {0, 0, 0};
     for (uint32_t t0 = 0; t0 < ntiles; t0 += groups * kCensusUnroll) {
         int32_t a[kCensusUnroll], br[kCensusUnroll], bd[kCensusUnroll];
@@ -1541,8 +1564,8 @@ __device__ __forceinline__ void contact_census(const Ctx &c, uint32_t tid)
             const uint32_t tile = t0 + u * groups + grp;
             a[u] = br[u] = bd[u] = -1;
             if (tile < ntiles) {
-                const uint32_t tr = tile / c.mtpr, tc = tile - tr * c.mtpr;
-                const uint32_t y = (tr << c.lg_mr) + oy, x = (tc << c.lg_mc) + ox;
+                const uint32_t tr = tile / c.mtpr(), tc = tile - tr * c.mtpr();
+                const uint32_t y = (tr << c.lg_mr) + oy, x = (tc << c.lg_mc()) + ox;
                 if (y < L && x < L) {
                     a[u] = c.map[((size_t)tile << 5) + off];
                     const uint32_t xr = x + 1 == L ? 0 : x + 1, yd = y + 1 == L ? 0 : y + 1;
@@ -1623,8 +1646,6 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
     c.wd = d.wd;
     c.flags = d.flags;
     c.sample = d.sample;
-    c.L2 = d.L * d.L;
-    c.ncap = c.L2 / d.k + 1;
     c.k0 = (uint32_t)d.seed;
     c.k1 = (uint32_t)(d.seed >> 32);
     c.fL = d.fL;
@@ -1632,26 +1653,14 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
     c.fC = d.fC;
     c.fwd = d.fwd;
     c.fwp = d.fwp;
-    c.wp = padded_words(d.L);
-    c.lp = padded_side(d.L);
     c.lg_tr = d.lg_tr;
-    c.lg_tw = 4 - d.lg_tr;
-    c.tr_m = (1u << c.lg_tr) - 1;
-    c.tw_m = (1u << c.lg_tw) - 1;
-    c.tpr = c.wp >> c.lg_tw;
     c.lg_mr = d.lg_mr;
-    c.lg_mc = 5 - d.lg_mr;
-    c.mr_m = (1u << c.lg_mr) - 1;
-    c.mc_m = (1u << c.lg_mc) - 1;
-    c.mtpr = c.lp >> c.lg_mc;
     c.spec_rows = d.spec_rows;
     SlabLayout s = slab_layout(d.L, d.k);
     c.av0 = (uint64_t *)(slab + s.avail0);
     c.av1 = (uint64_t *)(slab + s.avail1);
     c.sm0 = (uint64_t *)(slab + s.sum0);
     c.sm1 = (uint64_t *)(slab + s.sum1);
-    c.swp = summary_words(d.L);
-    c.sparse = d.sparse;
     c.map = (int32_t *)(slab + s.map);
     c.node = (int4 *)(slab + s.node);
     c.kmer = (uint32_t *)(slab + s.kmer);
@@ -1660,21 +1669,11 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
     c.cnt0 = (uint32_t *)(lds + l.cnt0);
     c.cnt1 = (uint32_t *)(lds + l.cnt1);
     c.cnt2 = (uint32_t *)(lds + l.cnt2);
-    c.n1 = l.n1;
-    c.n2 = l.n2;
     c.ring = (uint32_t *)(lds + l.ring);
     c.banc = (uint32_t *)(lds + l.banc);
     c.e_step = (uint32_t *)(lds + l.edges);
-    c.e_ms = c.e_step + kEdges;
-    c.e_vx = (int32_t *)(c.e_ms + kEdges);
-    c.e_vy = c.e_vx + kEdges;
     c.s_par = (uint32_t *)(lds + l.slots);
-    c.s_meta = c.s_par + kSlots;
-    c.s_gid = c.s_meta + kSlots;
-    c.s_dx = (int32_t *)(c.s_gid + kSlots);
-    c.s_dy = c.s_dx + kSlots;
     c.h_key = (uint32_t *)(lds + l.hash);
-    c.h_val = c.h_key + kHash;
 }
 
 // One sample on one workgroup.  deadline = 0 runs it from the empty lattice
@@ -1752,20 +1751,21 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             h->lab_stop = st->lab_stop;
             h->stop = 0;
             h->ncon[0] = h->ncon[1] = h->ncon[2] = 0;
+            for (int q = 0; q < 7; ++q) h->sel_acc[q] = 0;
         }
     } else {
         // ---- initial state (Sec. II.A): all sites empty, all placements free
         // the padded map (a multiple of 32 x 32 sites) is all -1
         int4 *m4 = (int4 *)c.map;
-        const size_t q4 = (size_t)c.lp * c.lp / 4;
+        const size_t q4 = (size_t)c.lp() * c.lp() / 4;
         for (size_t i = tid; i < q4; i += NT) m4[i] = make_int4(-1, -1, -1, -1);
         // bitmaps: every anchor of a real row and column available, padding 0
         const uint32_t wd = c.wd;
         const uint32_t tailbits = L & 63u;
         const uint64_t last = tailbits ? ((1ull << tailbits) - 1) : ~0ull;
-        const uint32_t nwords = c.lp * c.wp;
+        const uint32_t nwords = c.lp() * c.wp();
         for (uint32_t i = tid; i < nwords; i += NT) {
-            uint32_t row = fdiv(i, c.fwp), wi = i - row * c.wp;
+            uint32_t row = fdiv(i, c.fwp), wi = i - row * c.wp();
             uint64_t full = (row >= L || wi >= wd) ? 0ull : (wi == wd - 1 ? last : ~0ull);
             size_t at = bm_index(c, row, wi);
             c.av0[at] = full;
@@ -1773,9 +1773,9 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
         }
         if (SPARSE) {
             // summary bit set for every word of a real row and column
-            const uint32_t nsum = c.lp * c.swp;
+            const uint32_t nsum = c.lp() * c.swp();
             for (uint32_t i = tid; i < nsum; i += NT) {
-                uint32_t row = i / c.swp, sw = i - row * c.swp;
+                uint32_t row = i / c.swp(), sw = i - row * c.swp();
                 uint32_t lo = sw * 64, hi = lo + 64 < wd ? lo + 64 : wd;
                 uint64_t bits = (row >= L || lo >= wd) ? 0ull : (hi - lo == 64 ? ~0ull : ((1ull << (hi - lo)) - 1));
                 c.sm0[i] = bits;
@@ -1790,12 +1790,12 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             uint32_t c1 = r1 < L ? L : (r1 < rows ? vcount : 0);
             c.cnt0[i] = c0 | (c1 << 16);
         }
-        for (uint32_t g = tid; g < c.n1; g += NT) {
+        for (uint32_t g = tid; g < c.n1(); g += NT) {
             uint32_t lo = g * 64, hi = lo + 64 < rows ? lo + 64 : rows;
             uint32_t nh = hi <= L ? hi - lo : (lo >= L ? 0 : L - lo);
             c.cnt1[g] = nh * L + (hi - lo - nh) * vcount;
         }
-        for (uint32_t g = tid; g < c.n2; g += NT) {
+        for (uint32_t g = tid; g < c.n2(); g += NT) {
             uint32_t lo = g * 4096, hi = lo + 4096 < rows ? lo + 4096 : rows;
             uint32_t nh = hi <= L ? hi - lo : (lo >= L ? 0 : L - lo);
             c.cnt2[g] = nh * L + (hi - lo - nh) * vcount;
@@ -1825,6 +1825,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             h->lab_stop = 0;
             h->stop = stop;
             h->ncon[0] = h->ncon[1] = h->ncon[2] = 0;
+            for (int q = 0; q < 7; ++q) h->sel_acc[q] = 0;
         }
     }
     __syncthreads();
