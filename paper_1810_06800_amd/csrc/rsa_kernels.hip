@@ -430,12 +430,18 @@ __device__ __forceinline__ bool rect_round(const Ctx &c, const Rect &r, const Re
     return true;
 }
 
+struct NoHook {
+    __device__ __forceinline__ void operator()() const {}
+};
+
 // Wave wv of nwv clears its share of both rectangles, CAP words in flight
 // per lane: read the words, clear the blocked bits that are still set,
-// decrement the row counts by the bits cleared.
-template <int CAP>
+// decrement the row counts by the bits cleared.  hook() runs while the first
+// CAP reads are in flight; it must not touch memory (its instructions then
+// overlap the reads' latency).
+template <int CAP, typename Hook = NoHook>
 __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint32_t wv, uint32_t nwv,
-                                            uint32_t &wchg)
+                                            uint32_t &wchg, const Hook &hook = Hook())
 {
     const RectLane la = rect_lane(c, cl.a, wv, nwv);
     const RectLane lb = rect_lane(c, cl.b, wv, nwv);
@@ -443,6 +449,7 @@ __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint3
     uint64_t *const bma = bitmap(c, cl.a.o);
     uint64_t *const bmb = bitmap(c, cl.b.o);
     const uint32_t rba = cl.a.o * c.L, rbb = cl.b.o * c.L;
+    if (total == 0) hook();
     for (uint32_t base = 0; base < total; base += CAP) {
         uint64_t old[CAP];
 #pragma unroll
@@ -458,6 +465,7 @@ __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint3
                 ok = rect_round(c, cl.b, lb, rr - la.rounds, wv, nwv, row, at, mask);
             old[s] = ok ? (rr < la.rounds ? bma : bmb)[at] : 0;
         }
+        if (base == 0) hook();
 #pragma unroll
         for (int s = 0; s < CAP; ++s) {
             const uint32_t rr = base + s;
@@ -748,7 +756,8 @@ struct SpecRows {
 // the clear removes; C is estimated as the rectangles' area times the
 // available fraction A / 2L^2, and the window is centred half-way.
 template <int SPW>
-__device__ __forceinline__ void read_ahead(const Ctx &c, const Clear &cl, uint64_t u, SpecRows<SPW> &sp)
+__device__ __forceinline__ void read_ahead(const Ctx &c, const Clear &cl, uint64_t u, float inv2l2,
+                                           SpecRows<SPW> &sp)
 {
     const uint32_t lane = lane_id(), L = c.L, wd = c.wd;
     sp.nr = 0;
@@ -756,7 +765,7 @@ __device__ __forceinline__ void read_ahead(const Ctx &c, const Clear &cl, uint64
     const uint32_t A = scan_top(c, inc2, v2);
     if (A <= 1) return;
     const float area = (float)cl.a.nrows * (float)cl.a.len + (float)cl.b.nrows * (float)cl.b.len;
-    uint32_t C = uniform((uint32_t)(area * ((float)A / (2.0f * (float)L * (float)L))));
+    uint32_t C = uniform((uint32_t)(area * ((float)A * inv2l2)));
     C = C < A ? C : A - 1;
     const uint32_t r = draw_rank(u, A - C) + C / 2;
     if (!locate_row(c, inc2, v2, r < A ? r : A - 1, R, rin)) return;
@@ -831,6 +840,7 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
     uint32_t wchg = 0;
     const bool prof = c.prof != nullptr;
     unsigned long long *const acc = c.h->sel_acc;   // lane 0 adds to these when profiling
+    const float inv2l2 = 1.0f / (2.0f * (float)L * (float)L);   // read-ahead estimate only
     uint64_t p0 = 0;
     if (prof && lane == 0) acc[kAccStart] = tick();
     // draws for the 64 steps of t_begin's block (lane = step within the block)
@@ -877,20 +887,6 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         const uint32_t o = P >= c.L2() ? 1u : 0u;
         const uint32_t rem = P - o * c.L2();
         const uint32_t y = fdiv(rem, c.fL), x = rem - y * L;
-        seqh += mix64(((uint64_t)t << 32) | P);
-        for (uint32_t i = lane; i < k; i += 64) {
-            uint32_t s;
-            if (o == 0) {
-                uint32_t xx = x + i;
-                xx = xx >= L ? xx - L : xx;
-                s = y * L + xx;
-            } else {
-                uint32_t yy = y + i;
-                yy = yy >= L ? yy - L : yy;
-                s = yy * L + x;
-            }
-            occ += mix64(((uint64_t)s << 32) | t);
-        }
         const Clear cl = make_clear(c, o, y, x);
         if (NSEL > 1 && lane == 0) {
             c.h->cur_p = P;
@@ -903,19 +899,39 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         // read the rows where step t+1 will most likely pick, then clear:
         // the clear's reads are issued after the read-ahead's, so waiting for
         // them covers both
+        // hashes of the deposit: pure arithmetic, run while the clear's
+        // reads are in flight
+        const auto hash_step = [&] {
+            seqh += mix64(((uint64_t)t << 32) | P);
+            for (uint32_t i = lane; i < k; i += 64) {
+                uint32_t s;
+                if (o == 0) {
+                    uint32_t xx = x + i;
+                    xx = xx >= L ? xx - L : xx;
+                    s = y * L + xx;
+                } else {
+                    uint32_t yy = y + i;
+                    yy = yy >= L ? yy - L : yy;
+                    s = yy * L + x;
+                }
+                occ += mix64(((uint64_t)s << 32) | t);
+            }
+        };
         SpecRows<SPW == 0 ? 1 : SPW> sp;
         sp.nr = 0;
         uint64_t ph = prof ? tick() : 0;
-        if constexpr (SPW > 0) read_ahead<SPW>(c, cl, u1, sp);
+        if constexpr (SPW > 0) read_ahead<SPW>(c, cl, u1, inv2l2, sp);
         if (prof) {
             uint64_t ph1 = tick();
             if (lane == 0) acc[kAccHook] += ph1 - ph;
             ph = ph1;
         }
-        if constexpr (SPARSE)
+        if constexpr (SPARSE) {
+            hash_step();
             sparse_clear<CAP>(c, cl, 0, NSEL, wchg);
-        else
-            clear_items<CAP>(c, cl, 0, NSEL, wchg);
+        } else {
+            clear_items<CAP>(c, cl, 0, NSEL, wchg, hash_step);
+        }
         if (prof && lane == 0) acc[kAccProcess] += tick() - ph;
         if (NSEL > 1) {
             // helpers' bitmap stores must be visible before the next select
