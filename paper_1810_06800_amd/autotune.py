@@ -6,7 +6,7 @@ depend on it, so the tuner is free to pick the fastest: for each (L, k) it
 times batches of that shape on the GPU (HIP events around the kernels,
 best of ``reps``) under a forced tile, walking one coordinate at a time from
 the built-in heuristic's tile (waves, clear mode, bitmap tile, map tile), and
-keeps the fastest.  Every tile's results are compared with the first tile's,
+keeps the fastest, switching only for a clear gain (MARGIN).  Every tile's results are compared with the first tile's,
 field by field, and a difference aborts the run.
 
     python -m paper_1810_06800_amd.autotune [--out paper_1810_06800_amd/tiles.json]
@@ -37,6 +37,11 @@ SHAPES = [
     (32768, 4096, 8, 1),
 ]
 WAVES = (0, 1, 2, 3)          # wave-count indices tried (1, 2, 3, 7 selecting waves)
+# A tile replaces the incumbent only when it is this much faster: smaller
+# differences are run-to-run noise, and a needless change of tile shape can
+# raise the HBM traffic for nothing (2-row bitmap tiles at L = 1024, k = 64
+# read 65 % more bytes than 8-row ones at the same speed).
+MARGIN = 0.02
 LG_TR = (0, 1, 2, 3, 4)
 LG_MR = (0, 1, 2, 3, 4, 5)
 FIELDS = ("n_jam", "n_wrap_x", "n_wrap_y", "n_wrap_any", "occ_hash", "seq_hash", "alg_bytes",
@@ -96,7 +101,7 @@ def tune_shape(ctx, L: int, k: int, n: int, reps: int, log=print):
             parts[dim] = v
             t = encode(*parts)
             ms = measure(t)
-            if ms < best_ms:
+            if ms < best_ms * (1.0 - MARGIN):
                 best, best_ms = t, ms
     return {"L": L, "k": k, "tile": best, "shape": decode(best), "ms": best_ms,
             "heuristic_tile": start, "heuristic_ms": tried[start], "samples": n, "reps": reps,
@@ -127,7 +132,8 @@ def main(argv=None):
     ctx.close()
     out = {"device": torch.cuda.get_device_name(0), "seconds": round(time.time() - t0, 1),
            "method": "coordinate walk from the heuristic tile: waves, clear mode, bitmap tile rows, "
-                     "map tile rows; best of reps HIP-event kernel times per tile; results identical "
+                     "map tile rows; best of reps HIP-event kernel times per tile; a tile replaces "
+                     f"the incumbent only when {100 * MARGIN:g} % faster; results identical "
                      "across all tiles",
            "entries": entries}
     with open(a.out, "w") as f:

@@ -117,7 +117,9 @@ def test_autotune_table_is_well_formed(rsa):
         assert 0 <= e["tile"] < n
         tried = {int(k): v for k, v in e["tried"].items()}
         assert e["tile"] in tried and e["heuristic_tile"] in tried
-        assert tried[e["tile"]] == min(tried.values())
+        # the table's tile is the heuristic's unless another was clearly faster
+        assert tried[e["tile"]] <= tried[e["heuristic_tile"]]
+        assert tried[e["tile"]] <= min(tried.values()) * 1.05
         assert rsa.tile_shape(e["tile"])[0] in (1, 2, 3, 7)
     assert [(L, k, tile) for L, k, tile in rsa.load_tile_table()] == [
         (e["L"], e["k"], e["tile"]) for e in t["entries"]]
