@@ -451,21 +451,10 @@ __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint3
     const uint32_t rba = cl.a.o * c.L, rbb = cl.b.o * c.L;
     if (total == 0) hook();
     for (uint32_t base = 0; base < total; base += CAP) {
-        uint64_t old[CAP];
-#pragma unroll
-        for (int s = 0; s < CAP; ++s) {
-            const uint32_t rr = base + s;
-            uint32_t row = 0;
-            size_t at = 0;
-            uint64_t mask = 0;
-            bool ok = false;
-            if (rr < la.rounds)
-                ok = rect_round(c, cl.a, la, rr, wv, nwv, row, at, mask);
-            else if (rr < total)
-                ok = rect_round(c, cl.b, lb, rr - la.rounds, wv, nwv, row, at, mask);
-            old[s] = ok ? (rr < la.rounds ? bma : bmb)[at] : 0;
-        }
-        if (base == 0) hook();
+        // each lane's CAP words: address, mask of the blocked bits and count
+        // row are kept from the reads to the writes
+        uint64_t old[CAP], msk[CAP];
+        uint32_t idx[CAP], crow[CAP];
 #pragma unroll
         for (int s = 0; s < CAP; ++s) {
             const uint32_t rr = base + s;
@@ -478,10 +467,18 @@ __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint3
                 ok = rect_round(c, cl.a, la, rr, wv, nwv, row, at, mask);
             else if (rr < total)
                 ok = rect_round(c, cl.b, lb, rr - la.rounds, wv, nwv, row, at, mask);
-            const uint64_t hit = ok ? old[s] & mask : 0;
+            old[s] = ok ? (in_a ? bma : bmb)[at] : 0;
+            msk[s] = ok ? mask : 0;
+            idx[s] = (uint32_t)at;
+            crow[s] = (in_a ? rba : rbb) + row;
+        }
+        if (base == 0) hook();
+#pragma unroll
+        for (int s = 0; s < CAP; ++s) {
+            const uint64_t hit = old[s] & msk[s];
             if (hit) {
-                (in_a ? bma : bmb)[at] = old[s] & ~hit;
-                count_sub(c, (in_a ? rba : rbb) + row, (uint32_t)__popcll(hit));
+                (base + s < la.rounds ? bma : bmb)[idx[s]] = old[s] & ~hit;
+                count_sub(c, crow[s], (uint32_t)__popcll(hit));
                 ++wchg;
             }
         }
