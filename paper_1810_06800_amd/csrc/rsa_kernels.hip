@@ -245,16 +245,17 @@ struct Ctx {
 __device__ __forceinline__ uint64_t *bitmap(const Ctx &c, uint32_t o) { return o ? c.av1 : c.av0; }
 
 // Word w of bitmap row `row` inside its 128-byte tile.
-__device__ __forceinline__ size_t bm_index(const Ctx &c, uint32_t row, uint32_t w)
+// (32-bit: a bitmap holds at most 32768 x 528 words, a map 2^30 sites)
+__device__ __forceinline__ uint32_t bm_index(const Ctx &c, uint32_t row, uint32_t w)
 {
-    return (((size_t)(row >> c.lg_tr) * c.tpr() + (w >> c.lg_tw())) << 4) + ((row & c.tr_m()) << c.lg_tw()) +
+    return (((row >> c.lg_tr) * c.tpr() + (w >> c.lg_tw())) << 4) + ((row & c.tr_m()) << c.lg_tw()) +
            (w & c.tw_m());
 }
 
 // Site (y, x) of the map inside its 128-byte tile.
-__device__ __forceinline__ size_t map_index(const Ctx &c, uint32_t y, uint32_t x)
+__device__ __forceinline__ uint32_t map_index(const Ctx &c, uint32_t y, uint32_t x)
 {
-    return (((size_t)(y >> c.lg_mr) * c.mtpr() + (x >> c.lg_mc())) << 5) + ((y & c.mr_m()) << c.lg_mc()) +
+    return (((y >> c.lg_mr) * c.mtpr() + (x >> c.lg_mc())) << 5) + ((y & c.mr_m()) << c.lg_mc()) +
            (x & c.mc_m());
 }
 
@@ -404,7 +405,7 @@ __device__ __forceinline__ RectLane rect_lane(const Ctx &c, const Rect &r, uint3
 
 // Round rr of wave wv: the word this lane reads (row, bitmap index, mask).
 __device__ __forceinline__ bool rect_round(const Ctx &c, const Rect &r, const RectLane &rl, uint32_t rr,
-                                           uint32_t wv, uint32_t nwv, uint32_t &row, size_t &at,
+                                           uint32_t wv, uint32_t nwv, uint32_t &row, uint32_t &at,
                                            uint64_t &mask)
 {
     const uint32_t g = rr * nwv + wv;   // wave-uniform
@@ -416,7 +417,7 @@ __device__ __forceinline__ bool rect_round(const Ctx &c, const Rect &r, const Re
         if (i >= r.nrows || mask == 0) return false;
         row = r.row0 + i;
         row = row >= c.L ? row - c.L : row;
-        at = ((size_t)(row >> c.lg_tr) * c.tpr() << 4) + ((row & c.tr_m()) << c.lg_tw()) + rl.colpart;
+        at = (((row >> c.lg_tr) * c.tpr()) << 4) + ((row & c.tr_m()) << c.lg_tw()) + rl.colpart;
         return true;
     }
     i = g / rl.nchunk;
@@ -459,7 +460,7 @@ __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint3
         for (int s = 0; s < CAP; ++s) {
             const uint32_t rr = base + s;
             uint32_t row = 0;
-            size_t at = 0;
+            uint32_t at = 0;
             uint64_t mask = 0;
             bool ok = false;
             const bool in_a = rr < la.rounds;
@@ -542,7 +543,7 @@ __device__ __forceinline__ void sparse_rect(const Ctx &c, const Rect &r, uint32_
         }
 #pragma unroll
         for (int s = 0; s < CAP; ++s)
-            if (cand[s]) cand[s] &= sm[(size_t)srow[s] * c.swp() + ssw[s]];
+            if (cand[s]) cand[s] &= sm[srow[s] * c.swp() + ssw[s]];
         // data words, DCAP per lane per round
         for (;;) {
             bool any = false;
@@ -593,7 +594,7 @@ __device__ __forceinline__ void sparse_rect(const Ctx &c, const Rect &r, uint32_
         }
 #pragma unroll
         for (int s = 0; s < CAP; ++s)
-            if (zero[s]) atomicAnd((unsigned long long *)&sm[(size_t)srow[s] * c.swp() + ssw[s]], ~zero[s]);
+            if (zero[s]) atomicAnd((unsigned long long *)&sm[srow[s] * c.swp() + ssw[s]], ~zero[s]);
     }
 }
 
@@ -1780,7 +1781,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
         for (uint32_t i = tid; i < nwords; i += NT) {
             uint32_t row = fdiv(i, c.fwp), wi = i - row * c.wp();
             uint64_t full = (row >= L || wi >= wd) ? 0ull : (wi == wd - 1 ? last : ~0ull);
-            size_t at = bm_index(c, row, wi);
+            const uint32_t at = bm_index(c, row, wi);
             c.av0[at] = full;
             c.av1[at] = h_only ? 0ull : full;
         }
