@@ -552,17 +552,22 @@ __device__ __forceinline__ void sparse_rect(const Ctx &c, const Rect &r, uint32_
             if (__ballot(any) == 0) break;
             uint64_t old[DCAP];
             uint32_t pick[DCAP];   // item << 8 | word bit, or ~0
+            uint32_t dat[DCAP], dw[DCAP], drow[DCAP];   // word index, word column, row
 #pragma unroll
             for (int d = 0; d < DCAP; ++d) {
                 pick[d] = 0xFFFFFFFFu;
                 old[d] = 0;
+                dat[d] = dw[d] = drow[d] = 0;
 #pragma unroll
                 for (int s = 0; s < CAP; ++s) {
                     if (pick[d] == 0xFFFFFFFFu && cand[s] != 0) {
                         const uint32_t b = (uint32_t)(__ffsll((long long)cand[s]) - 1);
                         cand[s] &= cand[s] - 1;
                         pick[d] = ((uint32_t)s << 8) | b;
-                        old[d] = bm[bm_index(c, srow[s], ssw[s] * 64 + b)];
+                        dw[d] = ssw[s] * 64 + b;
+                        drow[d] = srow[s];
+                        dat[d] = bm_index(c, srow[s], dw[d]);
+                        old[d] = bm[dat[d]];
                     }
                 }
             }
@@ -570,18 +575,11 @@ __device__ __forceinline__ void sparse_rect(const Ctx &c, const Rect &r, uint32_
             for (int d = 0; d < DCAP; ++d) {
                 if (pick[d] == 0xFFFFFFFFu) continue;
                 const uint32_t s = pick[d] >> 8, b = pick[d] & 255u;
-                uint32_t row = 0, sw = 0;
-#pragma unroll
-                for (int q = 0; q < CAP; ++q)
-                    if ((uint32_t)q == s) {
-                        row = srow[q];
-                        sw = ssw[q];
-                    }
-                const uint32_t w = sw * 64 + b;
+                const uint32_t row = drow[d], w = dw[d];
                 const uint64_t hit = old[d] & col_mask(L, r.c0, r.len, w);
                 if (hit) {
                     const uint64_t nv = old[d] & ~hit;
-                    bm[bm_index(c, row, w)] = nv;
+                    bm[dat[d]] = nv;
                     count_sub(c, rowbase + row, (uint32_t)__popcll(hit));
                     ++wchg;
                     if (nv == 0) {
