@@ -1363,8 +1363,22 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track)
         }
         __builtin_amdgcn_wave_barrier();
         if (lane == 0) lds_store(&c.h->lab_progress, t1);
-        // site map of the batch
-        for (uint32_t q = lane; q < B * k; q += 64) {
+        // site map of the batch; long k-mers (sparse-clear kernels) walk
+        // each k-mer along its line, decoding its anchor once
+        if (SIDE && k >= kSideGather) {
+            for (uint32_t i = 0; i < B; ++i) {
+                const uint32_t a = uniform(lds_peek(&c.banc[i]));
+                const uint32_t om = a >> 31, site = a & 0x7FFFFFFFu;
+                const uint32_t ay = fdiv(site, c.fL), ax = site - ay * L;
+                const uint32_t along0 = om ? ay : ax;
+                for (uint32_t j = lane; j < k; j += 64) {
+                    uint32_t al = along0 + j;
+                    al = al >= L ? al - L : al;
+                    c.map[om ? map_index(c, al, ax) : map_index(c, ay, al)] = (int32_t)(tl + i);
+                }
+            }
+        }
+        for (uint32_t q = lane; !(SIDE && k >= kSideGather) && q < B * k; q += 64) {
             uint32_t i = fdiv(q, c.fk);
             uint32_t s = q - i * k;
             uint32_t a = c.banc[i];
