@@ -221,8 +221,8 @@ enum ProfSlot {
     kProfLabFlushes,    // count
     kProfSteps,         // count
     kProfSpecHits,      // count: next row read ahead of the clear was the right one
-    kProfSelHook,       // clear reads issued + read-ahead work (selecting wave)
-    kProfSelProcess,    // clear words back, bits cleared, counts updated
+    kProfSelHook,       // read-ahead of the next select's rows (selecting wave)
+    kProfSelProcess,    // the selecting wave's clear: reads, hashes, bits, counts
     kProfSlots
 };
 
