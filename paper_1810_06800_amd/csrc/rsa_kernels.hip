@@ -198,6 +198,7 @@ enum SelAcc { kAccStart = 0, kAccRing, kAccSelect, kAccClear, kAccHook, kAccProc
 struct Ctx {
     unsigned long long *prof;   // this sample's counters, or null
     uint32_t L, k, wd, flags, sample;
+    uint32_t ncap;     // k-mer records in the slab, L*L/k + 1
     uint32_t k0, k1;   // Philox key
     // bitmap tiles: 2^lg_tr rows x 2^(4-lg_tr) words; site-map tiles:
     // 2^lg_mr rows x 2^(5-lg_mr) sites (the rest is derived on use, which
@@ -218,7 +219,6 @@ struct Ctx {
     uint32_t *h_key;    // root hash: keys, then values (kHash each)
 
     __device__ __forceinline__ uint32_t L2() const { return L * L; }
-    __device__ __forceinline__ uint32_t ncap() const { return L * L / k + 1; }
     __device__ __forceinline__ uint32_t wp() const { return padded_words(L); }
     __device__ __forceinline__ uint32_t lp() const { return padded_side(L); }
     __device__ __forceinline__ uint32_t swp() const { return summary_words(L); }
@@ -865,13 +865,14 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         }
         // A correct run never deposits more than L*L/k k-mers; stop before
         // the k-mer records would overflow.
-        if (t + 1 >= c.ncap()) {
+        if (t + 1 >= c.ncap) {
             if (lane == 0) c.h->status = kErrSelect;
             break;
         }
-        if (t >= kRing) {
+        // every 64 steps: wait for ring room for the next 64 placements
+        if ((t & 63) == 0 && t + 64 > kRing) {
             if (prof) p0 = tick();
-            while (!lds_load(&c.h->lab_exit) && t - lds_load(&c.h->lab_progress) >= kRing)
+            while (!lds_load(&c.h->lab_exit) && t + 64 - lds_load(&c.h->lab_progress) > kRing)
                 __builtin_amdgcn_s_sleep(2);
             if (prof && lane == 0) acc[kAccRing] += tick() - p0;
         }
@@ -1045,7 +1046,7 @@ __device__ __forceinline__ bool global_find(const Ctx &c, uint32_t x, uint32_t &
             ok = true;
             break;
         }
-        if ((uint32_t)nd.x >= c.ncap()) break;   // not a k-mer id: corrupted record
+        if ((uint32_t)nd.x >= c.ncap) break;   // not a k-mer id: corrupted record
         ax += nd.y;
         ay += nd.z;
         cur = (uint32_t)nd.x;
@@ -1672,6 +1673,7 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
     c.wd = d.wd;
     c.flags = d.flags;
     c.sample = d.sample;
+    c.ncap = d.L * d.L / d.k + 1;
     c.k0 = (uint32_t)d.seed;
     c.k1 = (uint32_t)(d.seed >> 32);
     c.fL = d.fL;
