@@ -152,7 +152,7 @@ def main():
     def step():
         b = ctx.run_batch(descs)
         ms = ctx.elapsed_ms(b)
-        return ctx.results(b), ms
+        return ctx.results(b, as_array=True), ms
 
     for _ in range(args.warmup):
         step()
@@ -166,11 +166,12 @@ def main():
         print(f"# step {i}: kernel {ms:.2f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    bad = [r for r in results if r["status"] != 0]
-    if bad:
-        raise RuntimeError(f"{len(bad)} samples failed, first status {bad[0]['status']}")
-    deposits = sum(r["n_jam"] for r in results)
-    alg_bytes = sum(r["alg_bytes"] for r in results)
+    bad = results["status"] != 0
+    if bad.any():
+        raise RuntimeError(f"{int(bad.sum())} samples failed, first status {int(results['status'][bad][0])}")
+    deposits = int(results["n_jam"].sum())
+    alg_bytes = int(results["alg_bytes"].sum())
+    results = [{f: r[f].item() for f in results.dtype.names} for r in results]   # for the checks below
     value = deposits * args.steps / wall
     avg_ms = sum(kernel_ms) / len(kernel_ms)
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9

@@ -125,6 +125,33 @@ void give_block(rsa_ctx *c, Block b)
     if (b.ptr) c->pool.push_back(b);
 }
 
+void *take_pinned(rsa_ctx *c, size_t bytes)
+{
+    int best = -1;
+    for (size_t i = 0; i < c->pinned.size(); ++i) {
+        const size_t b = c->pinned[i].bytes;
+        if (b >= bytes && b <= 2 * bytes + 4096 && (best < 0 || b < c->pinned[best].bytes)) best = (int)i;
+    }
+    if (best >= 0) {
+        void *p = c->pinned[best].ptr;
+        c->pinned.erase(c->pinned.begin() + best);
+        return p;
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    return p;
+}
+
+void give_pinned(rsa_ctx *c, void *p, size_t bytes)
+{
+    if (!p) return;
+    if (c->pinned.size() >= 16) {   // keep a few for the next batches
+        (void)hipHostFree(c->pinned.front().ptr);
+        c->pinned.erase(c->pinned.begin());
+    }
+    c->pinned.push_back(Block{p, bytes});
+}
+
 int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, int census, uint32_t lds)
 {
     int nb = 0;
@@ -172,8 +199,8 @@ void destroy_batch(rsa_ctx *c, Batch *b)
     if (b->ev_start) (void)hipEventDestroy(b->ev_start);
     if (b->ev_end) (void)hipEventDestroy(b->ev_end);
     if (b->ev_done) (void)hipEventDestroy(b->ev_done);
-    if (b->h_desc) (void)hipHostFree(b->h_desc);
-    if (b->h_res) (void)hipHostFree(b->h_res);
+    give_pinned(c, b->h_desc, b->h_desc_bytes);
+    give_pinned(c, b->h_res, b->h_res_bytes);
     give_block(c, b->mem);
     delete b;
 }
@@ -479,8 +506,11 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
                            : nullptr;
 
     // ---- descriptors (pinned staging), copied before the call returns
-    if (hipHostMalloc((void **)&b->h_desc, desc_bytes, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&b->h_res, res_bytes, hipHostMallocDefault) != hipSuccess) {
+    b->h_desc = (DevDesc *)take_pinned(c, desc_bytes);
+    b->h_desc_bytes = desc_bytes;
+    b->h_res = (rsa_result_t *)take_pinned(c, res_bytes);
+    b->h_res_bytes = res_bytes;
+    if (!b->h_desc || !b->h_res) {
         destroy_batch(c, b.release());
         return fail(c, RSA_ENOMEM, "pinned host allocation failed");
     }
@@ -732,6 +762,7 @@ void rsa_destroy(rsa_ctx *c)
     c->batches.clear();
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     for (auto &b : c->pool) dev_free(c, b.ptr, b.bytes);
+    for (auto &b : c->pinned) (void)hipHostFree(b.ptr);
     for (int i = 0; i < kPlainStreams; ++i) {
         if (c->plain[i]) (void)hipStreamDestroy(c->plain[i]);
         if (c->join[i]) (void)hipEventDestroy(c->join[i]);

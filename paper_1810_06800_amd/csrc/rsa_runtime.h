@@ -72,6 +72,7 @@ struct Batch {
     Block mem;
     DevDesc *h_desc = nullptr;      // pinned
     rsa_result_t *h_res = nullptr;  // pinned
+    size_t h_desc_bytes = 0, h_res_bytes = 0;
     hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_done = nullptr;
     std::vector<Group> groups;
     int mode = RSA_MODE_BATCHED;
@@ -99,6 +100,7 @@ struct rsa_ctx {
     uint64_t next_id = 1;
     std::map<uint64_t, rsa::Batch *> batches;
     std::vector<rsa::Block> pool;   // free device blocks
+    std::vector<rsa::Block> pinned; // free pinned host buffers (descriptor / result staging)
     std::vector<rsa::GraphEntry> graphs;
     int64_t opt_mode = RSA_MODE_BATCHED, opt_tile = -1, opt_graph = 1, opt_slots = 0, opt_prof = 0;
     int clock_khz = 0;
@@ -123,6 +125,9 @@ int sample_tile(const rsa_ctx *c, uint32_t L, uint32_t k);
 // Device memory through the caller's allocator or hipMalloc, within the budget.
 bool take_block(rsa_ctx *c, size_t bytes, Block &out);
 void give_block(rsa_ctx *c, Block b);
+// Pinned host staging from the context's pool (nullptr if hipHostMalloc fails).
+void *take_pinned(rsa_ctx *c, size_t bytes);
+void give_pinned(rsa_ctx *c, void *p, size_t bytes);
 // Workgroups of a schedule's kernel resident on the whole device at once.
 int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, int census, uint32_t lds);
 // Kernel-side descriptor of a sample; `out` is its index in the result array.

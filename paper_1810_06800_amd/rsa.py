@@ -323,9 +323,10 @@ class Context:
             raise RsaError(rc, self.last_error())
         return [list(out[i * SIZE_BINS:(i + 1) * SIZE_BINS]) for i in range(n)]
 
-    def results(self, batch, wait: bool = True):
-        """Results of a batch as a list of dicts (None if not ready and
-        wait=False)."""
+    def results(self, batch, wait: bool = True, as_array: bool = False):
+        """Results of a batch as a list of dicts, or with as_array=True as a
+        numpy structured array with the fields of rsa_result_t (None if not
+        ready and wait=False)."""
         bid, n = batch
         out = (Result * max(n, 1))()
         rc = self._lib.rsa_results(self._h, bid, out, n, 1 if wait else 0)
@@ -333,6 +334,8 @@ class Context:
             return None
         if rc != RSA_OK:
             raise RsaError(rc, self.last_error())
+        if as_array:
+            return np.ctypeslib.as_array(out)[:n].copy()
         return [{f: getattr(out[i], f) for f in RESULT_FIELDS} for i in range(n)]
 
     def run(self, descs, stream=None):

@@ -137,6 +137,16 @@ def test_tiles_and_modes_agree(ctx, orc):
         ctx.set_option(rsa.OPT_SLOTS, 0)
 
 
+def test_results_as_array(ctx):
+    """The structured-array view of a batch's results equals the dicts."""
+    descs = [(64, 8, 5, s, 0) for s in range(6)]
+    want = ctx.run(descs)
+    arr = ctx.results(ctx.run_batch(descs), as_array=True)
+    assert len(arr) == len(want)
+    for r, w in zip(arr, want):
+        assert {f: r[f].item() for f in arr.dtype.names} == w
+
+
 def test_graph_replays_repeat(ctx, orc):
     """The same batch replayed from the cached graph gives the same results,
     with other work and synchronisations in between."""
