@@ -221,7 +221,7 @@ enum ProfSlot {
     kProfLabFlushes,    // count
     kProfSteps,         // count
     kProfSpecHits,      // count: next row read ahead of the clear was the right one
-    kProfSelHook,       // read-ahead of the next select's rows (selecting wave)
+    kProfSelHook,       // read-ahead of the next select's rows outside the clear
     kProfSelProcess,    // the selecting wave's clear: reads, hashes, bits, counts
     kProfSlots
 };

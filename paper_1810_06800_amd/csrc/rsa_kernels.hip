@@ -438,8 +438,8 @@ struct NoHook {
 // Wave wv of nwv clears its share of both rectangles, CAP words in flight
 // per lane: read the words, clear the blocked bits that are still set,
 // decrement the row counts by the bits cleared.  hook() runs while the first
-// CAP reads are in flight; it must not touch memory (its instructions then
-// overlap the reads' latency).
+// CAP reads are in flight; it may read LDS but not global memory (its
+// instructions then overlap the reads' latency).
 template <int CAP, typename Hook = NoHook>
 __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint32_t wv, uint32_t nwv,
                                             uint32_t &wchg, const Hook &hook = Hook())
@@ -746,16 +746,17 @@ struct SpecRows {
     uint32_t o, y0, nr;
 };
 
-// Read ahead the rows where the next placement is expected once the clear
-// `cl` has landed.  The next rank lies near u*(A - C)/2^64, and in the counts
-// before the clear up to C further on, where C is the number of placements
-// the clear removes; C is estimated as the rectangles' area times the
-// available fraction A / 2L^2, and the window is centred half-way.
+// Where to read ahead: the rows where the next placement is expected once
+// the clear `cl` has landed.  The next rank lies near u*(A - C)/2^64, and in
+// the counts before the clear up to C further on, where C is the number of
+// placements the clear removes; C is estimated as the rectangles' area times
+// the available fraction A / 2L^2, and the window is centred half-way.  LDS
+// only, so it can run while the clear's reads are in flight.
 template <int SPW>
-__device__ __forceinline__ void read_ahead(const Ctx &c, const Clear &cl, uint64_t u, float inv2l2,
+__device__ __forceinline__ void plan_ahead(const Ctx &c, const Clear &cl, uint64_t u, float inv2l2,
                                            SpecRows<SPW> &sp)
 {
-    const uint32_t lane = lane_id(), L = c.L, wd = c.wd;
+    const uint32_t L = c.L;
     sp.nr = 0;
     uint32_t inc2, v2, R, rin;
     const uint32_t A = scan_top(c, inc2, v2);
@@ -772,15 +773,24 @@ __device__ __forceinline__ void read_ahead(const Ctx &c, const Clear &cl, uint64
     sp.o = o;
     sp.y0 = y0;
     sp.nr = nr;
-    const uint64_t *bm = bitmap(c, o);
-    const uint32_t nq = nr * wd;
+}
+
+// Issue the reads of the planned window.  A word may be read before or after
+// the clear (or a helper wave's share of it) has written it: the select
+// patches the window with the clear's masks, so either value serves.
+template <int SPW>
+__device__ __forceinline__ void load_ahead(const Ctx &c, SpecRows<SPW> &sp)
+{
+    const uint32_t lane = lane_id(), wd = c.wd;
+    const uint64_t *bm = bitmap(c, sp.o);
+    const uint32_t nq = sp.nr * wd;
 #pragma unroll
     for (int j = 0; j < SPW; ++j) {
         uint32_t q = lane + 64 * j;
         uint64_t v = 0;
         if (q < nq) {
             uint32_t dr = fdiv(q, c.fwd);
-            v = bm[bm_index(c, y0 + dr, q - dr * wd)];
+            v = bm[bm_index(c, sp.y0 + dr, q - dr * wd)];
         }
         sp.w[j] = v;
     }
@@ -893,9 +903,6 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         const uint32_t t1 = t + 1;
         if ((t1 & 63) == 0) u_pre = philox_u64(t1 + lane, c.sample, c.k0, c.k1);
         const uint64_t u1 = bcast64(u_pre, t1 & 63);
-        // read the rows where step t+1 will most likely pick, then clear:
-        // the clear's reads are issued after the read-ahead's, so waiting for
-        // them covers both
         // hashes of the deposit: pure arithmetic, run while the clear's
         // reads are in flight
         const auto hash_step = [&] {
@@ -914,22 +921,41 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
                 occ += mix64(((uint64_t)s << 32) | t);
             }
         };
+        // The rows where step t+1 will most likely pick are read ahead.
+        // Dense clear: the window is planned (LDS scans) while the clear's
+        // reads are in flight and read after the clear, so its reads overlap
+        // the exact select's scans.  Sparse clear: planned and read first,
+        // then the clear's dependent round trips cover the window's.
         SpecRows<SPW == 0 ? 1 : SPW> sp;
         sp.nr = 0;
         uint64_t ph = prof ? tick() : 0;
-        if constexpr (SPW > 0) read_ahead<SPW>(c, cl, u1, inv2l2, sp);
-        if (prof) {
-            uint64_t ph1 = tick();
-            if (lane == 0) acc[kAccHook] += ph1 - ph;
-            ph = ph1;
-        }
         if constexpr (SPARSE) {
+            if constexpr (SPW > 0) {
+                plan_ahead<SPW>(c, cl, u1, inv2l2, sp);
+                load_ahead<SPW>(c, sp);
+            }
+            if (prof) {
+                uint64_t ph1 = tick();
+                if (lane == 0) acc[kAccHook] += ph1 - ph;
+                ph = ph1;
+            }
             hash_step();
             sparse_clear<CAP>(c, cl, 0, NSEL, wchg);
+            if (prof && lane == 0) acc[kAccProcess] += tick() - ph;
         } else {
-            clear_items<CAP>(c, cl, 0, NSEL, wchg, hash_step);
+            const auto hook = [&] {
+                hash_step();
+                if constexpr (SPW > 0) plan_ahead<SPW>(c, cl, u1, inv2l2, sp);
+            };
+            clear_items<CAP>(c, cl, 0, NSEL, wchg, hook);
+            if (prof) {
+                uint64_t ph1 = tick();
+                if (lane == 0) acc[kAccProcess] += ph1 - ph;
+                ph = ph1;
+            }
+            if constexpr (SPW > 0) load_ahead<SPW>(c, sp);
+            if (prof && lane == 0) acc[kAccHook] += tick() - ph;
         }
-        if (prof && lane == 0) acc[kAccProcess] += tick() - ph;
         if (NSEL > 1) {
             // helpers' bitmap stores must be visible before the next select
             uint32_t want = t1 * (NSEL - 1);
