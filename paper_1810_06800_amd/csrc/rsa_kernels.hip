@@ -379,11 +379,14 @@ struct RectLane {
     uint32_t nchunk;     // wide: 64-word chunks per row
 };
 
+// NARROW: every row has at most 64 words (L <= 4096), so no rectangle is
+// wide and the wide path is compiled out.
+template <bool NARROW>
 __device__ __forceinline__ RectLane rect_lane(const Ctx &c, const Rect &r, uint32_t wv, uint32_t nwv)
 {
     const uint32_t lane = lane_id();
     RectLane rl;
-    if (r.lg != 0xFFFFFFFFu) {
+    if (NARROW || r.lg != 0xFFFFFFFFu) {
         rl.rows_per = 64u >> r.lg;
         rl.rsub = lane >> r.lg;
         const uint32_t wsub = lane & ((1u << r.lg) - 1);
@@ -404,13 +407,14 @@ __device__ __forceinline__ RectLane rect_lane(const Ctx &c, const Rect &r, uint3
 }
 
 // Round rr of wave wv: the word this lane reads (row, bitmap index, mask).
+template <bool NARROW>
 __device__ __forceinline__ bool rect_round(const Ctx &c, const Rect &r, const RectLane &rl, uint32_t rr,
                                            uint32_t wv, uint32_t nwv, uint32_t &row, uint32_t &at,
                                            uint64_t &mask)
 {
     const uint32_t g = rr * nwv + wv;   // wave-uniform
     uint32_t i, w;
-    if (rl.nchunk == 0) {
+    if (NARROW || rl.nchunk == 0) {
         i = g * rl.rows_per + rl.rsub;
         mask = rl.mask;
         w = rl.w;
@@ -440,12 +444,12 @@ struct NoHook {
 // decrement the row counts by the bits cleared.  hook() runs while the first
 // CAP reads are in flight; it may read LDS but not global memory (its
 // instructions then overlap the reads' latency).
-template <int CAP, typename Hook = NoHook>
+template <int CAP, bool NARROW, typename Hook = NoHook>
 __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint32_t wv, uint32_t nwv,
                                             uint32_t &wchg, const Hook &hook = Hook())
 {
-    const RectLane la = rect_lane(c, cl.a, wv, nwv);
-    const RectLane lb = rect_lane(c, cl.b, wv, nwv);
+    const RectLane la = rect_lane<NARROW>(c, cl.a, wv, nwv);
+    const RectLane lb = rect_lane<NARROW>(c, cl.b, wv, nwv);
     const uint32_t total = la.rounds + lb.rounds;
     uint64_t *const bma = bitmap(c, cl.a.o);
     uint64_t *const bmb = bitmap(c, cl.b.o);
@@ -465,9 +469,9 @@ __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint3
             bool ok = false;
             const bool in_a = rr < la.rounds;
             if (in_a)
-                ok = rect_round(c, cl.a, la, rr, wv, nwv, row, at, mask);
+                ok = rect_round<NARROW>(c, cl.a, la, rr, wv, nwv, row, at, mask);
             else if (rr < total)
-                ok = rect_round(c, cl.b, lb, rr - la.rounds, wv, nwv, row, at, mask);
+                ok = rect_round<NARROW>(c, cl.b, lb, rr - la.rounds, wv, nwv, row, at, mask);
             old[s] = ok ? (in_a ? bma : bmb)[at] : 0;
             msk[s] = ok ? mask : 0;
             idx[s] = (uint32_t)at;
@@ -947,7 +951,7 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
                 hash_step();
                 if constexpr (SPW > 0) plan_ahead<SPW>(c, cl, u1, inv2l2, sp);
             };
-            clear_items<CAP>(c, cl, 0, NSEL, wchg, hook);
+            clear_items<CAP, ROWW == 1>(c, cl, 0, NSEL, wchg, hook);
             if (prof) {
                 uint64_t ph1 = tick();
                 if (lane == 0) acc[kAccProcess] += ph1 - ph;
@@ -1015,7 +1019,7 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
     }
 }
 
-template <int NSEL, bool SPARSE>
+template <int NSEL, int ROWW, bool SPARSE>
 __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
 {
     constexpr int CAP = TileCap<NSEL>::value;
@@ -1046,7 +1050,7 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
         if constexpr (SPARSE)
             sparse_clear<CAP>(c, cl, wv, NSEL, wchg);
         else
-            clear_items<CAP>(c, cl, wv, NSEL, wchg);
+            clear_items<CAP, ROWW == 1>(c, cl, wv, NSEL, wchg);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (lane == 0) atomicAdd(&c.h->clr_done, 1u);
     }
@@ -1889,7 +1893,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
     if (wave == 0)
         selector<NSEL, ROWW, SPARSE, CENSUS>(c, deadline);
     else if (wave < (uint32_t)NSEL)
-        helper<NSEL, SPARSE>(c, wave);
+        helper<NSEL, ROWW, SPARSE>(c, wave);
     else
         // the side-by-side gather is compiled into the sparse-clear kernels
         // only (long k-mers); it would raise the others' register count
