@@ -1346,11 +1346,20 @@ __device__ __forceinline__ void process_chunk(const Ctx &c, LabelState &ls, uint
     if (prof) prof_add(c, kProfLabMerge, tick() - p0);
 }
 
+// fill_map: a fresh sample's site map is still to be set to -1 (empty).
+// This wave does it before it reads or writes any site; the selecting
+// waves never touch the map, so they start without waiting for it.
 template <int G, bool SIDE>
-__device__ __forceinline__ void labeler(Ctx &c, bool track)
+__device__ __forceinline__ void labeler(Ctx &c, bool track, bool fill_map)
 {
     const uint32_t lane = lane_id();
     const uint32_t L = c.L, k = c.k, nC = 2 * k + 2;
+    if (fill_map) {
+        // the padded map (a multiple of 32 x 32 sites)
+        int4 *m4 = (int4 *)c.map;
+        const size_t q4 = (size_t)c.lp() * c.lp() / 4;
+        for (size_t i = lane; i < q4; i += 64) m4[i] = make_int4(-1, -1, -1, -1);
+    }
     const FastDiv fC = c.fC;
     LabelState ls;
     ls.nx = c.h->nx;
@@ -1812,11 +1821,8 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             for (int q = 0; q < 7; ++q) h->sel_acc[q] = 0;
         }
     } else {
-        // ---- initial state (Sec. II.A): all sites empty, all placements free
-        // the padded map (a multiple of 32 x 32 sites) is all -1
-        int4 *m4 = (int4 *)c.map;
-        const size_t q4 = (size_t)c.lp() * c.lp() / 4;
-        for (size_t i = tid; i < q4; i += NT) m4[i] = make_int4(-1, -1, -1, -1);
+        // ---- initial state (Sec. II.A): all placements free; all sites
+        // empty is written by the labelling wave (fill_map below)
         // bitmaps: every anchor of a real row and column available, padding 0
         const uint32_t wd = c.wd;
         const uint32_t tailbits = L & 63u;
@@ -1897,7 +1903,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
     else
         // the side-by-side gather is compiled into the sparse-clear kernels
         // only (long k-mers); it would raise the others' register count
-        labeler<(NSEL >= 7 && !CENSUS ? 16 : 8), SPARSE>(c, track || contacts || sizes_pass);
+        labeler<(NSEL >= 7 && !CENSUS ? 16 : 8), SPARSE>(c, track || contacts || sizes_pass, phase != 1);
     __syncthreads();
 
     if constexpr (CENSUS) {
