@@ -149,19 +149,25 @@ def main():
     ctx = rsa.Context(0)
     stream = torch.cuda.current_stream()
 
-    def step():
-        b = ctx.run_batch(descs)
+    def collect(b):
         ms = ctx.elapsed_ms(b)
         return ctx.results(b, as_array=True), ms
 
     for _ in range(args.warmup):
-        step()
+        collect(ctx.run_batch(descs))
     torch.cuda.synchronize()
     kernel_ms = []
     results = None
+    # Each step is one whole batch.  The next batch is enqueued before the
+    # current one is collected (batches are asynchronous and own their device
+    # memory), so its descriptor upload and launch overlap the running kernels
+    # and the result copy-back of the previous step.
     t0 = time.perf_counter()
+    pending = ctx.run_batch(descs)
     for i in range(args.steps):
-        results, ms = step()
+        following = ctx.run_batch(descs) if i + 1 < args.steps else None
+        results, ms = collect(pending)
+        pending = following
         kernel_ms.append(ms)
         print(f"# step {i}: kernel {ms:.2f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
