@@ -62,7 +62,9 @@ def cpu_baseline(descs, gpu_results, budget_s: float):
     """Time the oracle on a bounded sample of the workload; check parity on it."""
     import oracle
 
-    threads = os.cpu_count() or 1
+    # the host cores this process may use, at most 16 (one GPU's share of a
+    # shared host)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
     # size the sample from a short single-sample probe: about budget_s of CPU work
     t0 = time.perf_counter()
     oracle.run_many(descs[:1], threads=1)
