@@ -123,3 +123,20 @@ def test_autotune_table_is_well_formed(rsa):
         assert rsa.tile_shape(e["tile"])[0] in (1, 2, 3, 7)
     assert [(L, k, tile) for L, k, tile in rsa.load_tile_table()] == [
         (e["L"], e["k"], e["tile"]) for e in t["entries"]]
+
+
+def test_missing_library_fails_loudly():
+    """Without the built library the binding raises; there is no fallback."""
+    import subprocess
+    import sys
+
+    code = ("import paper_1810_06800_amd.rsa as r\n"
+            "r.LIB_PATH = '/nonexistent/librsa_hip.so'\n"
+            "r._lib = None\n"
+            "try:\n"
+            "    r.Context(0)\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert "raised:" in out.stdout and "missing" in out.stdout
