@@ -691,37 +691,58 @@ __device__ __forceinline__ bool locate_row(const Ctx &c, uint32_t inc2, uint32_t
     return R < 2 * c.L;
 }
 
-// The rin-th available placement of row R: canonical index, or false.
+// Position of the r-th (0-based) set bit of w, by halving with popcounts;
+// 64 + something when w has no more than r set bits.
+__device__ __forceinline__ uint32_t select_bit(uint64_t w, uint32_t r)
+{
+    const uint32_t n = (uint32_t)__popcll(w);
+    uint32_t pos = r < n ? 0u : 64u;
+    uint32_t c = (uint32_t)__popc((uint32_t)w);
+    uint32_t v = (uint32_t)w;
+    if (r >= c) {
+        r -= c;
+        v = (uint32_t)(w >> 32);
+        pos += 32;
+    }
+#pragma unroll
+    for (uint32_t half = 16; half >= 1; half >>= 1) {
+        c = (uint32_t)__popc(v & ((1u << half) - 1));
+        if (r >= c) {
+            r -= c;
+            v >>= half;
+            pos += half;
+        }
+    }
+    return pos;
+}
+
+// The rin-th available placement of row R: canonical index, or false.  Each
+// lane selects the bit its own residual rank points at while the wave finds
+// the lane that holds the placement; that lane's answer is read last.
 template <int ROWW>
 __device__ __forceinline__ bool pick_in_row(const Ctx &c, const RowWords<ROWW> &rw, uint32_t R, uint32_t rin,
                                             uint32_t &P)
 {
-    const uint32_t lane = lane_id();
     const uint32_t per = (c.wd + 63) >> 6;
-    uint64_t word = 0;
-    uint32_t wsel = 0;
+    uint32_t x = 0xFFFFFFFFu;
     bool found = false;
 #pragma unroll
     for (uint32_t j = 0; j < ROWW; ++j) {
         if (!found && j < per) {
-            uint32_t pc = (uint32_t)__popcll(rw.w[j]);
-            uint32_t pinc = wave_scan(pc);
-            uint32_t tot = bcast(pinc, 63);
+            const uint32_t pc = (uint32_t)__popcll(rw.w[j]);
+            const uint32_t pinc = wave_scan(pc);
+            const uint32_t tot = bcast(pinc, 63);
             if (rin < tot) {
-                uint32_t l = first_lane(__ballot(pinc > rin));
-                rin -= bcast(pinc - pc, l);
-                word = bcast64(rw.w[j], l);
-                wsel = l + 64 * j;
+                const uint32_t mine = select_bit(rw.w[j], rin - (pinc - pc));
+                const uint32_t l = first_lane(__ballot(pinc > rin));
+                const uint32_t pos = bcast(mine, l);
+                if (pos < 64) x = (l + 64 * j) * 64 + pos;
                 found = true;
             } else {
                 rin -= tot;
             }
         }
     }
-    uint32_t below = (uint32_t)__popcll(word & ((1ull << lane) - 1));
-    uint64_t bal = __ballot(((word >> lane) & 1) && below == rin);
-    if (!found || bal == 0) return false;
-    const uint32_t x = wsel * 64 + first_lane(bal);
     if (x >= c.L) return false;
     const uint32_t o = R >= c.L ? 1u : 0u;
     P = uniform(o * c.L2() + (R - o * c.L) * c.L + x);
