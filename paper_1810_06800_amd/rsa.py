@@ -95,6 +95,13 @@ def lib() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_1810_06800_amd.build` (hipcc, gfx950)")
+    # torch ships its own HIP runtime: load it first so that the library
+    # binds to the same one (loaded the other way round, two runtimes end up
+    # in the process and the library sees no device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
     L.rsa_create.argtypes = [ctypes.POINTER(vp), i32, u64, ctypes.POINTER(Allocator)]

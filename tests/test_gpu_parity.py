@@ -306,3 +306,22 @@ def test_invalid_descriptors_rejected(ctx):
     # the context still works afterwards
     assert ctx.run([(8, 2, 0, 0, 0)])[0]["status"] == 0
     assert ctx.run([]) == []
+
+
+def test_library_loaded_before_torch(orc):
+    """A process that loads the library before it imports torch still gets a
+    working context (one HIP runtime in the process), with exact results."""
+    import subprocess
+
+    code = ("from paper_1810_06800_amd import rsa\n"
+            "rsa.lib()\n"
+            "ctx = rsa.Context(0)\n"
+            "r = ctx.run([(24, 3, 11, 2, 0)])[0]\n"
+            "print('result', r['n_jam'], r['occ_hash'], r['n_wrap_any'], flush=True)\n"
+            "ctx.close()\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=240)
+    assert out.returncode == 0, out.stderr[-3000:]
+    want = orc.run(24, 3, 11, 2, 0)
+    line = [l for l in out.stdout.splitlines() if l.startswith("result")][0]
+    assert line.split()[1:] == [str(want["n_jam"]), str(want["occ_hash"]), str(want["n_wrap_any"])]
