@@ -325,3 +325,23 @@ def test_library_loaded_before_torch(orc):
     want = orc.run(24, 3, 11, 2, 0)
     line = [l for l in out.stdout.splitlines() if l.startswith("result")][0]
     assert line.split()[1:] == [str(want["n_jam"]), str(want["occ_hash"]), str(want["n_wrap_any"])]
+
+
+def test_all_statistics_together(ctx, orc):
+    """Cluster census, contact census and cluster sizes requested together
+    (flags 2 | 4 | 8) at the benchmark shape and a smaller one: every figure
+    matches the oracle's, and the counts are those of the flagless run."""
+    descs = [(1024, 64, 21, s, 14) for s in range(4)] + [(512, 32, 22, s, 14) for s in range(4)]
+    _log(f"all statistics: {len(descs)} samples")
+    want = orc.run_many([d[:4] + (d[4] & 7,) for d in descs], threads=min(16, os.cpu_count() or 1))
+    b = ctx.run_batch(descs)
+    hist = ctx.cluster_sizes(b)
+    got = ctx.results(b)
+    check(descs, got, want, census=True)
+    for d, g, w, h in zip(descs, got, want, hist):
+        assert (g["n_contacts_x"], g["n_contacts_y"], g["n_contacts_xy"]) == orc.contacts_at_jamming(*d[:4], 6), d
+        snap = orc.run(*d[:4], flags=6, snap_step=w["n_wrap_any"], snap_cap=d[0] * d[0] + 1)["snap_hist"]
+        assert h == size_bins(snap), d
+    plain = ctx.run([d[:4] + (0,) for d in descs])
+    for g, p in zip(got, plain):
+        assert all(g[f] == p[f] for f in FIELDS)
