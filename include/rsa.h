@@ -181,9 +181,9 @@ int rsa_batch_elapsed_ms(rsa_ctx *ctx, uint64_t batch_id, float *ms);
  * total / idle / map / gather / resolve / merge / write-back (ticks), then
  * labelling batches, edges, flushes, steps and rows read ahead correctly
  * (counts), then the select wave's read-ahead outside the clear (planning
- * and issuing the window's reads; the dense clear plans it during its own
- * reads) and its clear proper (reads, the deposit's hashes while they are in
- * flight, bits cleared, counts updated) (ticks).  Blocks until the kernels are done; valid until
+ * and issuing the window's reads; 0 with the dense clear, which does both
+ * inside) and its clear proper (reads, the deposit's hashes while they are
+ * in flight, bits cleared, counts updated) (ticks).  Blocks until the kernels are done; valid until
  * rsa_results.  RSA_EINVAL if the batch was not profiled or n differs from
  * its size. */
 int rsa_batch_profile(rsa_ctx *ctx, uint64_t batch_id, uint64_t *out, uint32_t n,

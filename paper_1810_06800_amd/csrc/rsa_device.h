@@ -221,7 +221,7 @@ enum ProfSlot {
     kProfLabFlushes,    // count
     kProfSteps,         // count
     kProfSpecHits,      // count: next row read ahead of the clear was the right one
-    kProfSelHook,       // read-ahead of the next select's rows outside the clear
+    kProfSelHook,       // read-ahead outside the clear (sparse clear; 0 with the dense one)
     kProfSelProcess,    // the selecting wave's clear: reads, hashes, bits, counts
     kProfSlots
 };

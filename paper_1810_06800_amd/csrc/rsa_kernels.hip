@@ -44,6 +44,13 @@ constexpr uint32_t kMaxHops = 64;   // union by rank keeps trees below log2(L^2)
 constexpr uint32_t kSideGather = 512;   // k from which contacts are gathered side by side
                                         // (sparse-clear kernels)
 
+// Loads whose latency must overlap other work are typed as global memory.
+// The slab pointers reach the kernel inside a struct, so the compiler cannot
+// infer their address space and emits FLAT loads; a FLAT result is waited
+// for with vmcnt(0), i.e. together with every load issued after it.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+
 // ---------------------------------------------------------------------------
 // Small device helpers
 // ---------------------------------------------------------------------------
@@ -443,10 +450,13 @@ struct NoHook {
 // per lane: read the words, clear the blocked bits that are still set,
 // decrement the row counts by the bits cleared.  hook() runs while the first
 // CAP reads are in flight; it may read LDS but not global memory (its
-// instructions then overlap the reads' latency).
-template <int CAP, bool NARROW, typename Hook = NoHook>
+// instructions then overlap the reads' latency).  landed() runs once those
+// reads are in, before their writes: loads it issues stay in flight through
+// the writes (no later wait covers them).
+template <int CAP, bool NARROW, typename Hook = NoHook, typename Hook2 = NoHook>
 __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint32_t wv, uint32_t nwv,
-                                            uint32_t &wchg, const Hook &hook = Hook())
+                                            uint32_t &wchg, const Hook &hook = Hook(),
+                                            const Hook2 &landed = Hook2())
 {
     const RectLane la = rect_lane<NARROW>(c, cl.a, wv, nwv);
     const RectLane lb = rect_lane<NARROW>(c, cl.b, wv, nwv);
@@ -454,8 +464,14 @@ __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint3
     uint64_t *const bma = bitmap(c, cl.a.o);
     uint64_t *const bmb = bitmap(c, cl.b.o);
     const uint32_t rba = cl.a.o * c.L, rbb = cl.b.o * c.L;
-    if (total == 0) hook();
-    for (uint32_t base = 0; base < total; base += CAP) {
+    if (total == 0) {
+        hook();
+        landed();
+        return;
+    }
+    // the first batch is peeled off the loop, so that its hooks sit in
+    // straight-line code between its reads and its writes
+    const auto batch = [&](uint32_t base, auto first) {
         // each lane's CAP words: address, mask of the blocked bits and count
         // row are kept from the reads to the writes
         uint64_t old[CAP], msk[CAP];
@@ -472,12 +488,16 @@ __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint3
                 ok = rect_round<NARROW>(c, cl.a, la, rr, wv, nwv, row, at, mask);
             else if (rr < total)
                 ok = rect_round<NARROW>(c, cl.b, lb, rr - la.rounds, wv, nwv, row, at, mask);
-            old[s] = ok ? (in_a ? bma : bmb)[at] : 0;
+            old[s] = ok ? ((const gmem<uint64_t> *)(in_a ? bma : bmb))[at] : 0;
             msk[s] = ok ? mask : 0;
             idx[s] = (uint32_t)at;
             crow[s] = (in_a ? rba : rbb) + row;
         }
-        if (base == 0) hook();
+        if constexpr (decltype(first)::value) {
+            hook();
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this batch's reads have landed
+            landed();
+        }
 #pragma unroll
         for (int s = 0; s < CAP; ++s) {
             const uint64_t hit = old[s] & msk[s];
@@ -487,7 +507,9 @@ __device__ __forceinline__ void clear_items(const Ctx &c, const Clear &cl, uint3
                 ++wchg;
             }
         }
-    }
+    };
+    batch(0u, std::true_type());
+    for (uint32_t base = CAP; base < total; base += CAP) batch(base, std::false_type());
 }
 
 // Sparse clear of one rectangle.  Per row, the rectangle's words fall in one
@@ -782,7 +804,7 @@ __device__ __forceinline__ void plan_ahead(const Ctx &c, const Clear &cl, uint64
                                            SpecRows<SPW> &sp)
 {
     const uint32_t L = c.L;
-    sp.nr = 0;
+    sp.o = sp.y0 = sp.nr = 0;
     uint32_t inc2, v2, R, rin;
     const uint32_t A = scan_top(c, inc2, v2);
     if (A <= 1) return;
@@ -800,24 +822,25 @@ __device__ __forceinline__ void plan_ahead(const Ctx &c, const Clear &cl, uint64
     sp.nr = nr;
 }
 
-// Issue the reads of the planned window.  A word may be read before or after
-// the clear (or a helper wave's share of it) has written it: the select
-// patches the window with the clear's masks, so either value serves.
+// Issue the reads of the planned window, without branches (a lane past the
+// window reads the window's first word and never hands it on), so that the
+// compiler keeps them in flight until the select takes a row from them.  A
+// word may be read before or after the clear (or a helper wave's share of
+// it) has written it: the select patches the window with the clear's masks,
+// so either value serves.
 template <int SPW>
 __device__ __forceinline__ void load_ahead(const Ctx &c, SpecRows<SPW> &sp)
 {
     const uint32_t lane = lane_id(), wd = c.wd;
-    const uint64_t *bm = bitmap(c, sp.o);
+    const gmem<uint64_t> *bm = (const gmem<uint64_t> *)bitmap(c, sp.o);
     const uint32_t nq = sp.nr * wd;
 #pragma unroll
     for (int j = 0; j < SPW; ++j) {
-        uint32_t q = lane + 64 * j;
-        uint64_t v = 0;
-        if (q < nq) {
-            uint32_t dr = fdiv(q, c.fwd);
-            v = bm[bm_index(c, sp.y0 + dr, q - dr * wd)];
-        }
-        sp.w[j] = v;
+        const uint32_t q0 = lane + 64 * j;
+        const uint32_t q = q0 < nq ? q0 : 0;   // in bounds: row y0 < L, word 0
+        const uint32_t dr = fdiv(q, c.fwd);
+        const uint64_t v = bm[bm_index(c, sp.y0 + dr, q - dr * wd)];
+        sp.w[j] = v;   // words past the window are never taken from it
     }
 }
 
@@ -948,11 +971,12 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         };
         // The rows where step t+1 will most likely pick are read ahead.
         // Dense clear: the window is planned (LDS scans) while the clear's
-        // reads are in flight and read after the clear, so its reads overlap
-        // the exact select's scans.  Sparse clear: planned and read first,
-        // then the clear's dependent round trips cover the window's.
+        // reads are in flight and read as soon as they have landed, so its
+        // reads overlap the clear's writes and the exact select's scans.
+        // Sparse clear: planned and read first, then the clear's dependent
+        // round trips cover the window's.
         SpecRows<SPW == 0 ? 1 : SPW> sp;
-        sp.nr = 0;
+        sp.o = sp.y0 = sp.nr = 0;
         uint64_t ph = prof ? tick() : 0;
         if constexpr (SPARSE) {
             if constexpr (SPW > 0) {
@@ -972,14 +996,11 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
                 hash_step();
                 if constexpr (SPW > 0) plan_ahead<SPW>(c, cl, u1, inv2l2, sp);
             };
-            clear_items<CAP, ROWW == 1>(c, cl, 0, NSEL, wchg, hook);
-            if (prof) {
-                uint64_t ph1 = tick();
-                if (lane == 0) acc[kAccProcess] += ph1 - ph;
-                ph = ph1;
-            }
-            if constexpr (SPW > 0) load_ahead<SPW>(c, sp);
-            if (prof && lane == 0) acc[kAccHook] += tick() - ph;
+            const auto landed = [&] {
+                if constexpr (SPW > 0) load_ahead<SPW>(c, sp);
+            };
+            clear_items<CAP, ROWW == 1>(c, cl, 0, NSEL, wchg, hook, landed);
+            if (prof && lane == 0) acc[kAccProcess] += tick() - ph;
         }
         if (NSEL > 1) {
             // helpers' bitmap stores must be visible before the next select
