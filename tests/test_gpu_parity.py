@@ -345,3 +345,17 @@ def test_all_statistics_together(ctx, orc):
     plain = ctx.run([d[:4] + (0,) for d in descs])
     for g, p in zip(got, plain):
         assert all(g[f] == p[f] for f in FIELDS)
+
+
+def test_full_ring_kmers_at_the_row_width_limit(ctx, orc):
+    """k = L on both sides of the one-wave row limit (L = 4096 and 4097):
+    every deposit covers a whole ring, the first one wraps in its own
+    direction and the other direction wraps only at jamming (n = L)."""
+    descs = [(4096, 4096, 5, 0, 2), (4096, 4096, 5, 1, 2), (4097, 4097, 5, 0, 2)]
+    _log(f"k = L at the row-width limit: {descs}")
+    want = [orc.run(*d) for d in descs]
+    got = ctx.run(descs)
+    check(descs, got, want, census=True)
+    for d, g in zip(descs, got):
+        assert g["n_jam"] == d[0] and g["n_wrap_any"] == 1
+        assert max(g["n_wrap_x"], g["n_wrap_y"]) == d[0]
