@@ -359,3 +359,20 @@ def test_full_ring_kmers_at_the_row_width_limit(ctx, orc):
     for d, g in zip(descs, got):
         assert g["n_jam"] == d[0] and g["n_wrap_any"] == 1
         assert max(g["n_wrap_x"], g["n_wrap_y"]) == d[0]
+
+
+def test_small_budget_reuses_slabs(orc):
+    """A context whose memory budget holds only a few slabs runs a larger
+    batch with a few workgroups, each taking sample after sample on the same
+    slab (every sample re-initialised), with exact results."""
+    from paper_1810_06800_amd import rsa
+
+    descs = [(256, 8, 31, s, 0) for s in range(40)] + [(300, 5, 32, s, 2) for s in range(8)]
+    foot = max(rsa.footprint_bytes(256, 8), rsa.footprint_bytes(300, 5))
+    small = rsa.Context(0, budget_bytes=6 * foot + (8 << 20))
+    try:
+        _log(f"small budget: {len(descs)} samples, budget {6 * foot + (8 << 20)} B")
+        got = small.run(descs)
+    finally:
+        small.close()
+    check(descs, got, orc.run_many(descs, threads=min(16, os.cpu_count() or 1)), census=True)
