@@ -13,7 +13,8 @@ is recomputed from scratch after every deposit, straight from the definition:
   with their unwrapped offset closes a cycle that winds round the torus
   (Sec. II.D, Newman-Ziff style).
 
-Only for tiny lattices (L <= 12 or so).
+The full run with windings is only for tiny lattices (L <= 12 or so); the
+availability-only and 2k-test runs reach L of a few hundred.
 """
 from __future__ import annotations
 
@@ -193,3 +194,153 @@ def run(L: int, k: int, seed: int, sample: int, h_only: bool = False, snap_step:
         "orient": orient,
         "snap_hist": snap_hist,
     }
+
+
+def _fits(occ: np.ndarray, k: int, h_only: bool = False) -> np.ndarray:
+    """Availability as a (2, L, L) boolean array: [o, y, x] is True when the
+    placement (o, y, x) has k empty sites."""
+    free = ~occ
+    fits = np.ones((2,) + occ.shape, dtype=bool)
+    for i in range(k):
+        fits[0] &= np.roll(free, -i, axis=1)
+        fits[1] &= np.roll(free, -i, axis=0)
+    if h_only:
+        fits[1] = False
+    return fits
+
+
+def changed_words(before: np.ndarray, after: np.ndarray) -> int:
+    """Number of 64-bit availability words (orientation, row, column // 64)
+    holding at least one placement whose availability differs."""
+    diff = before != after
+    L = diff.shape[2]
+    W = (L + 63) // 64
+    pad = np.zeros((2, L, W * 64), dtype=bool)
+    pad[:, :, :L] = diff
+    return int(pad.reshape(2, L, W, 64).any(axis=3).sum())
+
+
+def word_changes(L: int, k: int, seed: int, sample: int, h_only: bool = False) -> dict:
+    """Run the chain with availability recomputed from the occupancy after
+    every deposit (no windings) and count, per step, the availability words
+    whose value changes (Sec. II.B: each deposit makes every placement that
+    covers one of its sites unviable).  Returns n_jam, the total changed-word
+    count, and the number of availability bits that went from 1 to 0."""
+    occ = np.zeros((L, L), dtype=bool)
+    fits = _fits(occ, k, h_only)
+    total_words = 0
+    cleared = 0
+    t = 0
+    while True:
+        av = np.flatnonzero(fits.ravel())
+        A = len(av)
+        if A == 0:
+            break
+        u = draw_u(seed, sample, t)
+        P = int(av[(u * A) >> 64])
+        o, rem = divmod(P, L * L)
+        y, x = divmod(rem, L)
+        for i in range(k):
+            sy, sx = ((y + i) % L, x) if o else (y, (x + i) % L)
+            occ[sy, sx] = True
+        new = _fits(occ, k, h_only)
+        assert not (new & ~fits).any()   # availability only ever drops
+        total_words += changed_words(fits, new)
+        cleared += int((fits & ~new).sum())
+        fits = new
+        t += 1
+    return {"n_jam": t, "wchg_words": total_words, "bits_cleared": cleared}
+
+
+def clusters_with_positions(occ: np.ndarray):
+    """Clusters of occupied sites with breadth-first unwrapped coordinates:
+    (label grid, {site: (ux, uy)}, [wraps per cluster]).  A cluster wraps when
+    some edge disagrees with the offset of its two ends."""
+    L = occ.shape[0]
+    label = -np.ones((L, L), dtype=np.int64)
+    pos = {}
+    wraps = []
+    for sy in range(L):
+        for sx in range(L):
+            if not occ[sy, sx] or label[sy, sx] >= 0:
+                continue
+            c = len(wraps)
+            w = False
+            label[sy, sx] = c
+            pos[(sy, sx)] = (sx, sy)
+            q = deque([(sy, sx)])
+            while q:
+                y, x = q.popleft()
+                ux, uy = pos[(y, x)]
+                for ex, ey in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                    ny, nx = (y + ey) % L, (x + ex) % L
+                    if not occ[ny, nx]:
+                        continue
+                    want = (ux + ex, uy + ey)
+                    if label[ny, nx] < 0:
+                        label[ny, nx] = c
+                        pos[(ny, nx)] = want
+                        q.append((ny, nx))
+                    elif pos[(ny, nx)] != want:
+                        w = True
+            wraps.append(w)
+    return label, pos, wraps
+
+
+def paper_wrap_test(L: int, k: int, seed: int, sample: int) -> dict:
+    """Run the chain and, at every deposit, apply the Sec. II.D test: for each
+    pair of sites of one (not yet wrapping) cluster that the new k-mer touches,
+    |x1 - x2| + |y1 - y2| over their unwrapped coordinates above 2k means a
+    wrap.  Alongside, the exact winding of the cycle the pair closes through
+    the new k-mer: (unwrapped offset of the two sites) minus (their offset
+    along the new k-mer).  Returns the first step where the 2k test fires
+    (1-based, -1 if never) and the number of pairs where the two disagree."""
+    occ = np.zeros((L, L), dtype=bool)
+    t = 0
+    first = -1
+    pairs = disagree = 0
+    wrapped_before = False
+    while True:
+        fits = _fits(occ, k)
+        av = np.flatnonzero(fits.ravel())
+        A = len(av)
+        if A == 0:
+            break
+        u = draw_u(seed, sample, t)
+        P = int(av[(u * A) >> 64])
+        o, rem = divmod(P, L * L)
+        y, x = divmod(rem, L)
+        label, pos, wraps = clusters_with_positions(occ)
+        wrapped_before = wrapped_before or any(wraps)
+        # contacts: (cluster, unwrapped site position, offset from the anchor
+        # through the new k-mer)
+        ux, uy = (1, 0) if o == 0 else (0, 1)
+        touch = {}
+        for i in range(k):
+            ay, ax = (y + i * uy) % L, (x + i * ux) % L
+            for ex, ey in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                by, bx = (ay + ey) % L, (ax + ex) % L
+                if not occ[by, bx]:
+                    continue
+                c = int(label[by, bx])
+                touch.setdefault(c, []).append((pos[(by, bx)], (i * ux + ex, i * uy + ey)))
+        fired = False
+        for c, lst in touch.items():
+            if wraps[c]:
+                continue
+            for a in range(len(lst)):
+                for b in range(a + 1, len(lst)):
+                    (p1, r1), (p2, r2) = lst[a], lst[b]
+                    manhattan = abs(p1[0] - p2[0]) + abs(p1[1] - p2[1])
+                    wx = (p1[0] - p2[0]) - (r1[0] - r2[0])
+                    wy = (p1[1] - p2[1]) - (r1[1] - r2[1])
+                    paper = manhattan > 2 * k
+                    pairs += 1
+                    disagree += int(paper != (wx != 0 or wy != 0))
+                    fired = fired or paper
+        for i in range(k):
+            occ[(y + i * uy) % L, (x + i * ux) % L] = True
+        if fired and first < 0 and not wrapped_before:
+            first = t + 1
+        t += 1
+    return {"n_jam": t, "first_2k": first, "pairs": pairs, "disagree": disagree}
