@@ -4,16 +4,27 @@
 One step = one batch of the whole hot path (init, draw, select, deposit and
 clear, contacts + union-find + wrap check, result) over the workload, from
 descriptors in host memory to results back; every input lives in HBM while
-the kernels run.  The default workload is L = 1024, k = 64, 1024 samples
-(seeds 0..1023): the plain-path-at-scale configuration.
+the kernels run.  The default workload is L = 16384, k = 1024, 32 samples
+(seed 4): the largest single-GPU configuration, on which the HBM target is
+set.  ``--workload`` names the others (plain_small, plain_scale, mixed_batch,
+large_32k).
 
 The JSON line also carries
-  roofline      the persistent kernel's algorithmic bytes per launch (the
-                model in include/rsa.h, summed over the batch) divided by its
-                HIP-event duration, against 8 TB/s HBM
+  roofline      the persistent kernel's algorithmic bytes per launch divided
+                by its HIP-event duration, against 8 TB/s HBM and against the
+                streaming rate a plain copy reaches on the same device.  Per
+                sample: 4L^2 (site map) + 16 L ceil(L/64) (both availability
+                bitmaps) initialised, per deposit 4k (site map) + 4(2k+2)
+                (contacts) + 8 ceil(L/64) (select row) + 64 (union-find
+                records), 16 B per availability word whose value changes, and
+                4L^2 for one scan of the final occupancy; the library's own
+                record (alg_bytes) leaves out that scan (the hash is summed
+                at deposit time) and counts 16 B of union-find per deposit,
+                and is reported beside it
   cpu_baseline  the serial CPU oracle on a bounded sample of the same
                 workload on the host's cores (rank 0, N = 1 only)
-  plain         the per-sample-launch form on a subset of the same workload
+  plain         the per-sample-launch form and the batched form on the same
+                subset of the workload (its first 64 samples)
   serving       open-loop replays of request traces through the request
                 server (continuous batching): p50/p99 latency, served
                 deposits/s, offered vs served load
@@ -59,28 +70,80 @@ def describe(workload: str, descs) -> str:
 
 
 def cpu_baseline(descs, gpu_results, budget_s: float):
-    """Time the oracle on a bounded sample of the workload; check parity on it."""
+    """Time the oracle on a bounded sample of the workload; check parity on it.
+
+    The first round runs one sample per host thread; if it took less than
+    half the budget, a second round of more samples, sized from the first,
+    fills the rest.  Throughput is deposits over the wall time of both."""
     import oracle
 
-    # the host cores this process may use, at most 16 (one GPU's share of a
-    # shared host)
+    # the host cores this process may use, at most 16: a GPU box allots 16
+    # host cores to each GPU, so that is the whole share of one GPU
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
-    # size the sample from a short single-sample probe: about budget_s of CPU work
+    n1 = min(threads, len(descs))
     t0 = time.perf_counter()
-    oracle.run_many(descs[:1], threads=1)
-    one = max(time.perf_counter() - t0, 1e-4)
-    n = max(threads, min(len(descs), int(budget_s / one)))
-    n = min(n, len(descs))
-    sample = descs[:n]
-    t0 = time.perf_counter()
-    res = oracle.run_many(sample, threads=threads)
+    res = oracle.run_many(descs[:n1], threads=threads)
     wall = time.perf_counter() - t0
+    n = n1
+    if wall < budget_s / 2 and n1 < len(descs):
+        per_round = max(wall, 1e-4)
+        n2 = min(len(descs) - n1, int((budget_s - wall) / per_round) * n1)
+        if n2 > 0:
+            t0 = time.perf_counter()
+            res += oracle.run_many(descs[n1:n1 + n2], threads=threads)
+            wall += time.perf_counter() - t0
+            n += n2
     deposits = sum(r["n_jam"] for r in res)
     fields = ("n_jam", "n_wrap_x", "n_wrap_y", "n_wrap_any", "occ_hash", "seq_hash", "alg_bytes")
     exact = sum(all(g[f] == w[f] for f in fields) for g, w in zip(gpu_results[:n], res))
     return {"value": deposits / wall, "unit": "deposits/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} of {len(descs)} samples, serial per sample, one per thread",
+            "cpu_model": cpu_model(),
             "wall_s": round(wall, 3), "parity": f"{exact}/{n} bit-exact"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_rate_gbs(mib: int = 4096, reps: int = 5) -> float:
+    """Streaming rate of a plain device copy (read + write bytes over its
+    HIP-event time, best of reps): the achievable HBM rate on this machine."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * mib * (1 << 20) / (best * 1e-3) / 1e9
+
+
+def survey_bytes(descs, results) -> int:
+    """Algorithmic bytes of the batch in the per-sample model described at the
+    top: the library's alg_bytes plus 4L^2 for the final occupancy scan and
+    48 more bytes of union-find records per deposit."""
+    total = 0
+    for d, r in zip(descs, results):
+        L = d[0]
+        total += int(r["alg_bytes"]) + 4 * L * L + 48 * int(r["n_jam"])
+    return total
 
 
 def serving_run(ctx, trace, window_s: float, quantum_us: int, arena_frac: float, label: str):
@@ -121,7 +184,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="plain_scale")
+    ap.add_argument("--workload", default="large_16k")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-sample launch form")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="CPU seconds of oracle work")
@@ -180,9 +243,11 @@ def main():
     deposits = int(results["n_jam"].sum())
     alg_bytes = int(results["alg_bytes"].sum())
     results = [{f: r[f].item() for f in results.dtype.names} for r in results]   # for the checks below
+    model_bytes = survey_bytes(descs, results)
     value = deposits * args.steps / wall
     avg_ms = sum(kernel_ms) / len(kernel_ms)
-    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    achieved = model_bytes / (avg_ms * 1e-3) / 1e9
+    copy_gbs = copy_rate_gbs()
     traffic = measured_traffic(args.workload)
     out = {
         "metric": "deposits/s to jamming with p_c tracking",
@@ -202,10 +267,21 @@ def main():
                    "kernel_ms_per_step": avg_ms, "kernel_deposits_per_s": deposits / (avg_ms * 1e-3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "rsa_persistent", "alg_bytes_per_launch": alg_bytes},
+                     "kernel": "rsa_persistent", "kernel_ms": avg_ms,
+                     "alg_bytes_per_launch": model_bytes,
+                     "library_alg_bytes_per_launch": alg_bytes,
+                     "library_model_gbs": alg_bytes / (avg_ms * 1e-3) / 1e9,
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                     "traffic_gbs": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9},
     }
     if not args.no_plain:
+        # both forms on the same samples: the first 64 of the workload
         sub = descs[: min(len(descs), 64)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bres = ctx.run(sub)
+        torch.cuda.synchronize()
+        bw = time.perf_counter() - t1
         ctx.set_option(rsa.OPT_MODE, rsa.MODE_PLAIN)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -213,9 +289,10 @@ def main():
         torch.cuda.synchronize()
         pw = time.perf_counter() - t1
         ctx.set_option(rsa.OPT_MODE, rsa.MODE_BATCHED)
-        same = sum(p == r for p, r in zip(pres, results[: len(sub)]))
+        same = sum(p == r for p, r in zip(pres, bres))
         out["plain"] = {"value": sum(r["n_jam"] for r in pres) / pw, "unit": "deposits/s",
                         "samples": len(sub), "launches": len(sub), "streams": 4,
+                        "batched_same_samples": sum(r["n_jam"] for r in bres) / bw,
                         "identical_to_batched": f"{same}/{len(sub)}"}
     if args.serve_window > 0:
         try:

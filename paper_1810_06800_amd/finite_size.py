@@ -61,8 +61,9 @@ def extrapolate(points, key: str):
     return {"value": a, "stderr": ea, "slope": b}
 
 
-def run_grid(ctx, ks, ratios, samples: int, seed: int = 7, log=None):
-    """Runs every (k, L = r*k) cell as one batch; returns the table."""
+def run_grid(ctx, ks, ratios, samples: int, seed: int = 7, log=None, keep: bool = False):
+    """Runs every (k, L = r*k) cell as one batch; returns the table (with
+    keep=True each row also holds the cell's descriptors and raw results)."""
     rows = []
     for k in ks:
         for r in ratios:
@@ -83,6 +84,9 @@ def run_grid(ctx, ks, ratios, samples: int, seed: int = 7, log=None):
             dep = sum(x["n_jam"] for x in res)
             rows.append({"k": k, "L": L, "samples": samples, "pc": pcm, "pc_sem": pce, "pj": pjm,
                          "pj_sem": pje, "seconds": dt, "deposits_per_s": dep / dt})
+            if keep:
+                rows[-1]["descs"] = descs
+                rows[-1]["results"] = res
             if log:
                 log(f"k={k} L={L}: p_c {pcm:.4f} +- {pce:.4f}  p_j {pjm:.4f} +- {pje:.4f}  ({dt:.2f} s)")
     return rows

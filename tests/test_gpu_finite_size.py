@@ -5,6 +5,7 @@ Table I is measured at L = 100k with single runs, so the comparison is
 statistical and loose: the jamming coverage at L/k = 64 within 0.003 (its
 finite-size shift is O(1/L), Eq. 10), and p_c extrapolated with Eq. 9 within
 0.02.  The runs are seeded, so the numbers are the same on every machine.
+Every run of every cell is also compared with the oracle, field by field.
 """
 import os
 
@@ -34,9 +35,20 @@ def test_thresholds_against_table_one():
     assert torch.cuda.is_available()
     ctx = rsa.Context(0)
     try:
-        rows = fs.run_grid(ctx, [1, 2, 4, 8], [32, 64], 64, log=lambda m: print(m, flush=True))
+        rows = fs.run_grid(ctx, [1, 2, 4, 8], [32, 64], 64, log=lambda m: print(m, flush=True),
+                           keep=True)
     finally:
         ctx.close()
+    import oracle
+
+    fields = ("n_jam", "n_wrap_x", "n_wrap_y", "n_wrap_any", "occ_hash", "seq_hash", "alg_bytes",
+              "wchg_words")
+    for row in rows:
+        want = oracle.run_many(row["descs"], threads=16)
+        for d, g, w in zip(row["descs"], row["results"], want):
+            assert w["status"] == 0
+            for f in fields:
+                assert g[f] == w[f], (d, f, g[f], w[f])
     fits = fs.fits(rows)
     paper = table1()
     for k in (1, 2, 4, 8):
