@@ -7,8 +7,10 @@ by default, torch's caching allocator for device memory.  It raises
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Iterable, Sequence
 
 import numpy as np
@@ -206,7 +208,16 @@ def _torch_allocator(device: int):
             return None
 
     def free(ptr, _nbytes, _user):
-        torch.cuda.caching_allocator_delete(ptr)
+        # a context finalised while the interpreter shuts down may outlive
+        # torch's module state; its memory goes back with the process then
+        cuda = getattr(torch, "cuda", None)
+        delete = getattr(cuda, "caching_allocator_delete", None) if cuda is not None else None
+        if delete is None:
+            return
+        try:
+            delete(ptr)
+        except Exception:
+            pass
 
     fa, ff = ALLOC_FN(alloc), FREE_FN(free)
     return Allocator(fa, ff, None), (fa, ff)
@@ -221,6 +232,18 @@ def load_tile_table(path: str = TILE_TABLE):
     with open(path) as f:
         t = json.load(f)
     return [(int(e["L"]), int(e["k"]), int(e["tile"])) for e in t["entries"]]
+
+
+_live_contexts: "weakref.WeakSet" = None
+
+
+def _close_live_contexts():
+    """atexit hook: destroy contexts still open, while torch is intact."""
+    for ctx in list(_live_contexts or ()):
+        try:
+            ctx.close()
+        except Exception:
+            pass
 
 
 class Context:
@@ -250,6 +273,11 @@ class Context:
         if rc != RSA_OK:
             raise RsaError(rc, "rsa_create")
         self._h = handle
+        global _live_contexts
+        if _live_contexts is None:
+            _live_contexts = weakref.WeakSet()
+            atexit.register(_close_live_contexts)
+        _live_contexts.add(self)
         self.set_tile_table(load_tile_table(tile_table) if tile_table else [])
 
     def set_tile_table(self, entries) -> None:
