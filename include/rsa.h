@@ -160,6 +160,38 @@ size_t rsa_footprint_bytes(uint32_t L, uint32_t k);
 int rsa_run_batch(rsa_ctx *ctx, const rsa_sample_t *s, uint32_t n, void *hip_stream,
                   uint64_t *batch_id);
 
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation while they run.
+ *
+ * rsa_run_batch_static runs the samples of rsa_run_batch with the same
+ * kernels and schedules and gives the same results, but allocates nothing:
+ * no device, pinned or host-heap memory, no events, no graphs.  Its device
+ * state (work-queue counters, kernel-side descriptors, one slab per resident
+ * workgroup) lives in a static array of RSA_STATIC_SCRATCH_BYTES per device,
+ * held from the library's load to the end of the process.  Descriptors reach
+ * the device as kernel arguments.
+ *   s          host array of n descriptors, read before the call returns
+ *   d_results  DEVICE memory of n rsa_result_t, owned by the caller; written
+ *              in descriptor order when the stream reaches the end of the
+ *              call's kernels (no host copy; synchronise the stream first)
+ *   hip_stream the caller's hipStream_t (NULL = null stream)
+ * Samples sharing a kernel run in one persistent launch, launches one after
+ * another on the stream.  Every call on a device shares that device's array
+ * and leaves its contents behind; the call zeroes what must start at zero.
+ * Calls that overlap on one device (other streams, other contexts) race and
+ * give undefined results: the caller orders them.  RSA_EINVAL for a NULL
+ * argument, an invalid descriptor, RSA_FLAG_CLUSTER_SIZES (a two-pass feature
+ * of rsa_run_batch) or n > RSA_STATIC_MAX_SAMPLES; RSA_ENOMEM when one
+ * sample's slab does not fit the array (the message names the sizes);
+ * RSA_EDEVICE when the array's address could not be obtained at rsa_create
+ * or a launch fails.  RSA_OPT_MODE, RSA_OPT_GRAPH and RSA_OPT_PROFILE do not
+ * apply; tiles follow the context as in rsa_run_batch. */
+#define RSA_STATIC_SCRATCH_BYTES (128u << 20)
+#define RSA_STATIC_MAX_SAMPLES 2048
+int rsa_run_batch_static(rsa_ctx *ctx, const rsa_sample_t *s, uint32_t n, rsa_result_t *d_results,
+                         void *hip_stream);
+
 /* Copy the n results of batch `batch_id` into out[0..n-1] (same order as the
  * descriptors) and release the batch's device memory.  wait = 1 blocks until
  * the batch is done; wait = 0 returns RSA_ENOTREADY if it is still running

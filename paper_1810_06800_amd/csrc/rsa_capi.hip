@@ -7,7 +7,57 @@
 // per-context pool of slabs, through the caller's allocator when one is given.
 #include "rsa_runtime.h"
 
+#include <mutex>
+
+// Static scratch of rsa_run_batch_static: work-queue counters, kernel-side
+// descriptors and the per-workgroup slabs of a batch, for callers that cannot
+// allocate.  Each device holds its own copy for the life of the process; host
+// code reaches it only through the address hipGetSymbolAddress returns for the
+// device (kept in rsa_ctx::scratch), never through this name.
+static __device__ __align__(256) uint8_t scratch[RSA_STATIC_SCRATCH_BYTES];
+
 namespace rsa {
+
+// Kernel-side descriptors of rsa_run_batch_static travel as kernel arguments
+// (the launch copies them), kStageDescs per launch, into the static scratch.
+constexpr uint32_t kStageDescs = 24;
+struct StageArgs {
+    DevDesc d[kStageDescs];
+    DevDesc *dst;
+    uint32_t n;
+};
+static_assert(sizeof(StageArgs) <= 4096, "kernel argument size");
+
+__global__ void rsa_stage_descs(StageArgs a)
+{
+    const uint32_t i = threadIdx.x;
+    if (i < a.n) a.dst[i] = a.d[i];
+}
+
+// Device address of the static scratch on `device` (current), looked up once
+// per device.
+constexpr int kMaxScratchDevices = 64;
+static void *g_scratch[kMaxScratchDevices];
+static std::mutex g_scratch_mu;
+
+static void *scratch_address(int device, std::string &err)
+{
+    if (device < 0 || device >= kMaxScratchDevices) {
+        err = "device index beyond the scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch[device] = p;
+    }
+    return g_scratch[device];
+}
 
 const void *persistent_kernel(int waves, int wide, int sparse, int census)
 {
@@ -330,6 +380,9 @@ int rsa_create(rsa_ctx **out, int device, uint64_t hbm_budget_bytes, const rsa_a
         delete c;
         return RSA_EDEVICE;
     }
+    // the device is current: look up its static scratch (only
+    // rsa_run_batch_static needs it, which reports a failure here)
+    c->scratch = scratch_address(device, c->scratch_error);
     *out = c;
     return RSA_OK;
 }
@@ -683,6 +736,119 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     *batch_id = b->id;
     c->batches[b->id] = b.get();
     b.release();
+    return RSA_OK;
+}
+
+int rsa_run_batch_static(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, rsa_result_t *d_results,
+                         void *hip_stream)
+{
+    if (!c || (n > 0 && (!s || !d_results))) return fail(c, RSA_EINVAL, "null argument");
+    if (c->poisoned) return fail(c, RSA_EDEVICE, "context poisoned by an earlier device error");
+    if (n > RSA_STATIC_MAX_SAMPLES)
+        return fail(c, RSA_EINVAL, "rsa_run_batch_static takes at most " +
+                                       std::to_string(RSA_STATIC_MAX_SAMPLES) + " samples per call");
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!valid_sample(s[i]))
+            return fail(c, RSA_EINVAL, "invalid descriptor at index " + std::to_string(i));
+        if (s[i].flags & RSA_FLAG_CLUSTER_SIZES)
+            return fail(c, RSA_EINVAL, "RSA_FLAG_CLUSTER_SIZES needs rsa_run_batch (index " +
+                                           std::to_string(i) + ")");
+    }
+    if (!c->scratch) return fail(c, RSA_EDEVICE, "no static scratch on this device: " + c->scratch_error);
+    if (n == 0) return RSA_OK;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+
+    // ---- plan on the stack: group by kernel, longest samples first inside a
+    // group (the order rsa_run_batch uses), groups one after another
+    uint16_t order[RSA_STATIC_MAX_SAMPLES];
+    uint8_t key[RSA_STATIC_MAX_SAMPLES];
+    int16_t tile[RSA_STATIC_MAX_SAMPLES];
+    float cost[RSA_STATIC_MAX_SAMPLES];
+    for (uint32_t i = 0; i < n; ++i) {
+        tile[i] = (int16_t)sample_tile(c, s[i].L, s[i].k);
+        key[i] = (uint8_t)kernel_key(tile_waves(tile[i]), s[i].L > 4096 ? 1 : 0, tile_sparse(tile[i]),
+                                     (s[i].flags & RSA_FLAG_CONTACTS) ? 1 : 0);
+        cost[i] = (float)sample_cost(s[i].L, s[i].k, tile[i]);
+        order[i] = (uint16_t)i;
+    }
+    std::sort(order, order + n, [&](uint16_t a, uint16_t b) {
+        if (key[a] != key[b]) return key[a] > key[b];
+        if (cost[a] != cost[b]) return cost[a] > cost[b];
+        return a < b;
+    });
+    // scratch: queue counters, descriptors, then the slabs of one group at a time
+    const size_t queue_bytes = 256;
+    const size_t desc_bytes = align256((size_t)n * sizeof(DevDesc));
+    const size_t slab_base = queue_bytes + desc_bytes;
+    uint8_t *base = (uint8_t *)c->scratch;
+    uint32_t *d_queue = (uint32_t *)base;
+    DevDesc *d_desc = (DevDesc *)(base + queue_bytes);
+    struct StaticGroup {
+        int key;
+        uint32_t first, count, grid, lds;
+        size_t stride;
+    };
+    StaticGroup groups[2 * kKernelVariants * kNumWaveTiles];
+    uint32_t ng = 0;
+    for (uint32_t i = 0; i < n;) {
+        uint32_t j = i;
+        size_t stride = 0;
+        uint32_t lds = 0;
+        while (j < n && key[order[j]] == key[order[i]]) {
+            const rsa_sample_t &x = s[order[j]];
+            stride = std::max(stride, slab_layout(x.L, x.k).total);
+            lds = std::max(lds, lds_layout(x.L).total);
+            ++j;
+        }
+        StaticGroup g;
+        g.key = key[order[i]];
+        g.first = i;
+        g.count = j - i;
+        g.stride = stride;
+        g.lds = lds;
+        if (lds + 64 > c->lds_max) return fail(c, RSA_EINVAL, "lattice too large for LDS");
+        if (slab_base + stride > (size_t)RSA_STATIC_SCRATCH_BYTES)
+            return fail(c, RSA_ENOMEM, "a sample needs " + std::to_string(stride) +
+                                           " bytes of slab; the static scratch holds " +
+                                           std::to_string((size_t)RSA_STATIC_SCRATCH_BYTES - slab_base) +
+                                           " after the descriptors");
+        const uint32_t fit = (uint32_t)(((size_t)RSA_STATIC_SCRATCH_BYTES - slab_base) / stride);
+        const int waves = g.key >> 3, wide = (g.key >> 2) & 1, sparse = (g.key >> 1) & 1, census = g.key & 1;
+        g.grid = std::min(std::min(g.count, fit), (uint32_t)resident_blocks(c, waves, wide, sparse, census, lds));
+        if (c->opt_slots > 0) g.grid = std::min<uint32_t>(g.grid, (uint32_t)c->opt_slots);
+        groups[ng++] = g;
+        i = j;
+    }
+    // ---- launches on the caller's stream: counters zeroed by a kernel, the
+    // descriptors staged through kernel arguments, then one persistent launch
+    // per group in stream order (each group reuses the slab region)
+    uint32_t nq = (uint32_t)(queue_bytes / 4);
+    void *rargs[] = {&d_queue, &nq};
+    HIP_TRY(c, hipLaunchKernel(kResetKernel, dim3(1), dim3(256), rargs, 0, stream));
+    for (uint32_t i0 = 0; i0 < n; i0 += kStageDescs) {
+        StageArgs sa;
+        sa.n = std::min<uint32_t>(kStageDescs, n - i0);
+        sa.dst = d_desc + i0;
+        for (uint32_t q = 0; q < sa.n; ++q) sa.d[q] = make_dev_desc(s[order[i0 + q]], order[i0 + q], tile[order[i0 + q]]);
+        void *sargs[] = {&sa};
+        HIP_TRY(c, hipLaunchKernel((const void *)&rsa_stage_descs, dim3(1), dim3(kStageDescs), sargs, 0, stream));
+    }
+    for (uint32_t gi = 0; gi < ng; ++gi) {
+        const StaticGroup &g = groups[gi];
+        const int waves = g.key >> 3, wide = (g.key >> 2) & 1, sparse = (g.key >> 1) & 1, census = g.key & 1;
+        KernelArgs a{};
+        a.descs = d_desc + g.first;
+        a.n = g.count;
+        a.tile = (uint32_t)waves;
+        a.queue = d_queue + gi;
+        a.slabs = base + slab_base;
+        a.slab_stride = g.stride;
+        a.results = (DevResult *)d_results;
+        void *kargs[] = {&a};
+        HIP_TRY(c, hipLaunchKernel(persistent_kernel(waves, wide, sparse, census), dim3(g.grid),
+                                   dim3(64 * (kTileWaves[waves] + 1)), kargs, g.lds, stream));
+    }
     return RSA_OK;
 }
 

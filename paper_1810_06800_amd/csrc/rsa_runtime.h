@@ -108,6 +108,11 @@ struct rsa_ctx {
     hipEvent_t fork = nullptr, join[rsa::kPlainStreams] = {};
     int resident[rsa::kNumTiles][4] = {};   // cached occupancy per tile and LDS class
     std::map<std::pair<uint32_t, uint32_t>, int> tile_table;   // (L, k) -> measured best tile
+    // device address of this device's static scratch array (rsa_run_batch_static),
+    // looked up once per device when the first context on it is created; null
+    // (with scratch_error set) if the lookup failed
+    void *scratch = nullptr;
+    std::string scratch_error;
 };
 
 namespace rsa {

@@ -39,7 +39,9 @@ EXPORTS = ("rsa_create", "rsa_footprint_bytes", "rsa_run_batch", "rsa_results",
            "rsa_strerror", "rsa_last_error", "rsa_set_option", "rsa_get_option", "rsa_num_tiles",
            "rsa_tile_for_shape", "rsa_tile_shape", "rsa_set_tile_table", "rsa_tile_for_sample",
            "rsa_server_create", "rsa_server_submit", "rsa_server_step", "rsa_server_completed",
-           "rsa_server_results", "rsa_server_stats", "rsa_server_destroy")
+           "rsa_server_results", "rsa_server_stats", "rsa_server_destroy", "rsa_run_batch_static")
+STATIC_SCRATCH_BYTES = 128 << 20   # RSA_STATIC_SCRATCH_BYTES
+STATIC_MAX_SAMPLES = 2048          # RSA_STATIC_MAX_SAMPLES
 
 
 class Sample(ctypes.Structure):
@@ -112,6 +114,8 @@ def lib() -> ctypes.CDLL:
     L.rsa_footprint_bytes.restype = ctypes.c_size_t
     L.rsa_run_batch.argtypes = [vp, ctypes.POINTER(Sample), u32, vp, ctypes.POINTER(u64)]
     L.rsa_run_batch.restype = i32
+    L.rsa_run_batch_static.argtypes = [vp, ctypes.POINTER(Sample), u32, vp, vp]
+    L.rsa_run_batch_static.restype = i32
     L.rsa_results.argtypes = [vp, u64, ctypes.POINTER(Result), u32, i32]
     L.rsa_results.restype = i32
     L.rsa_batch_elapsed_ms.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_float)]
@@ -325,6 +329,36 @@ class Context:
         if rc != RSA_OK:
             raise RsaError(rc, self.last_error())
         return bid.value, n
+
+    def run_batch_static(self, descs, out=None, stream=None):
+        """rsa_run_batch_static: enqueue samples with no allocation inside the
+        library; results go to ``out``, a device tensor of at least
+        n * sizeof(rsa_result_t) bytes (a fresh uint8 tensor from torch when
+        None).  Returns ``out``; read it with ``static_results`` after the
+        stream has reached it."""
+        import torch
+
+        arr, n = make_samples(descs)
+        nbytes = n * ctypes.sizeof(Result)
+        if out is None:
+            out = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+        if not out.is_cuda or out.numel() * out.element_size() < nbytes or not out.is_contiguous():
+            raise ValueError("out must be a contiguous device tensor of n * sizeof(rsa_result_t) bytes")
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc = self._lib.rsa_run_batch_static(self._h, arr, n, ctypes.c_void_p(out.data_ptr()),
+                                            ctypes.c_void_p(stream))
+        if rc != RSA_OK:
+            raise RsaError(rc, self.last_error())
+        return out
+
+    @staticmethod
+    def static_results(out, n: int) -> list[dict]:
+        """Results written by run_batch_static into ``out`` (copied to the host
+        on the current stream)."""
+        raw = out.view(-1)[: n * ctypes.sizeof(Result)].cpu().numpy().tobytes()
+        arr = (Result * max(n, 1)).from_buffer_copy(raw.ljust(max(n, 1) * ctypes.sizeof(Result), b"\0"))
+        return [{f: getattr(arr[i], f) for f in RESULT_FIELDS} for i in range(n)]
 
     def elapsed_ms(self, batch) -> float:
         bid = batch[0] if isinstance(batch, tuple) else batch

@@ -140,3 +140,11 @@ def test_missing_library_fails_loudly():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
     assert out.returncode == 0, out.stderr[-2000:]
     assert "raised:" in out.stdout and "missing" in out.stdout
+
+
+def test_static_scratch_constants(rsa):
+    text = open(HEADER).read()
+    m = re.search(r"#define RSA_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == rsa.STATIC_SCRATCH_BYTES
+    m = re.search(r"#define RSA_STATIC_MAX_SAMPLES (\d+)", text)
+    assert m and int(m.group(1)) == rsa.STATIC_MAX_SAMPLES

@@ -1,0 +1,56 @@
+"""GPU: rsa_run_batch_static, the entry point that allocates nothing (its
+state lives in a static device array), against rsa_run_batch on the same
+context: two calls in a row, the second smaller, every field equal; and its
+refusals (a slab larger than the array, the two-pass cluster-size flag, too
+many samples) leave nothing enqueued."""
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_static_entry_point_matches_run_batch():
+    import torch
+
+    from paper_1810_06800_amd import rsa
+
+    assert torch.cuda.is_available()
+    ctx = rsa.Context(0)
+    try:
+        first = [(64, 8, 1, s, 0) for s in range(96)]
+        first += [(256, 16, 2, s, 2) for s in range(40)]
+        first += [(100, 10, 3, s, 4) for s in range(30)]
+        first += [(L, k, 4, 1, 0) for L, k in [(1, 1), (5, 3), (12, 12), (33, 4), (65, 65), (130, 9)]]
+        first += [(1024, 64, 5, s, 0) for s in range(6)] + [(300, 7, 6, 0, 1)]
+        second = [(48, 6, 7, s, 0) for s in range(12)] + [(512, 32, 8, s, 0) for s in range(3)]
+        for name, descs in (("first", first), ("second", second)):
+            _log(f"static entry point, {name} call: {len(descs)} samples")
+            out = ctx.run_batch_static(descs)
+            torch.cuda.synchronize()
+            got = ctx.static_results(out, len(descs))
+            want = ctx.run(descs)
+            for d, g, w in zip(descs, got, want):
+                assert g["status"] == 0, (d, g["status"])
+                assert g == w, (d, g, w)
+        # refusals: nothing is enqueued and the next call still works
+        with pytest.raises(rsa.RsaError) as e:
+            ctx.run_batch_static([(8192, 512, 1, 0, 0)])
+        assert e.value.code == rsa.RSA_ENOMEM
+        with pytest.raises(rsa.RsaError) as e:
+            ctx.run_batch_static([(64, 8, 1, 0, rsa.FLAG_CLUSTER_SIZES)])
+        assert e.value.code == rsa.RSA_EINVAL
+        with pytest.raises(rsa.RsaError) as e:
+            ctx.run_batch_static([(8, 2, 1, s, 0) for s in range(rsa.STATIC_MAX_SAMPLES + 1)])
+        assert e.value.code == rsa.RSA_EINVAL
+        descs = [(64, 8, 9, s, 0) for s in range(5)]
+        out = ctx.run_batch_static(descs)
+        torch.cuda.synchronize()
+        assert ctx.static_results(out, 5) == ctx.run(descs)
+    finally:
+        ctx.close()
