@@ -214,7 +214,18 @@ int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, int census, uint
     return nb * c->cus;
 }
 
-DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile)
+bool use_interval(uint32_t L, uint32_t k, int tile, size_t lds_max)
+{
+    return tile_sparse(tile) && k <= kIntervalMaxK && has_buckets(L, k) &&
+           (size_t)lds_layout(L).total + interval_lds_bytes(k) + 64 <= lds_max;
+}
+
+uint32_t sample_lds(uint32_t L, uint32_t k, int tile, size_t lds_max)
+{
+    return lds_layout(L).total + (use_interval(L, k, tile, lds_max) ? interval_lds_bytes(k) : 0u);
+}
+
+DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile, size_t lds_max)
 {
     DevDesc d;
     std::memset(&d, 0, sizeof(d));
@@ -230,6 +241,8 @@ DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile)
     d.fC = make_fastdiv(2 * s.k + 2);
     d.fwd = make_fastdiv(d.wd);
     d.fwp = make_fastdiv(padded_words(s.L));
+    d.fB = make_fastdiv(s.k + 1);
+    d.interval = use_interval(s.L, s.k, tile, lds_max) ? 1u : 0u;
     d.tile = (uint32_t)tile;
     d.sparse = (uint32_t)tile_sparse(tile);
     d.lg_tr = (uint32_t)tile_lg_tr(tile);
@@ -499,7 +512,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         while (j < ne && keys[order[j]] == keys[order[i]] && ent_pass[order[j]] == ent_pass[order[i]]) {
             const rsa_sample_t &x = s[ent_sample[order[j]]];
             stride = std::max(stride, slab_layout(x.L, x.k).total);
-            lds = std::max(lds, lds_layout(x.L).total);
+            lds = std::max(lds, sample_lds(x.L, x.k, tiles[ent_sample[order[j]]], c->lds_max));
             ++j;
         }
         g.count = j - i;
@@ -569,7 +582,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     }
     for (uint32_t i = 0; i < ne; ++i) {
         const uint32_t si = ent_sample[order[i]];
-        b->h_desc[i] = make_dev_desc(s[si], si, tiles[si]);
+        b->h_desc[i] = make_dev_desc(s[si], si, tiles[si], c->lds_max);
         if (ent_pass[order[i]]) b->h_desc[i].flags |= kDescSizesPass;
     }
     HIP_TRY(c, hipEventCreate(&b->ev_start));
@@ -798,7 +811,7 @@ int rsa_run_batch_static(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, rsa_resu
         while (j < n && key[order[j]] == key[order[i]]) {
             const rsa_sample_t &x = s[order[j]];
             stride = std::max(stride, slab_layout(x.L, x.k).total);
-            lds = std::max(lds, lds_layout(x.L).total);
+            lds = std::max(lds, sample_lds(x.L, x.k, tile[order[j]], c->lds_max));
             ++j;
         }
         StaticGroup g;
@@ -830,7 +843,7 @@ int rsa_run_batch_static(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, rsa_resu
         StageArgs sa;
         sa.n = std::min<uint32_t>(kStageDescs, n - i0);
         sa.dst = d_desc + i0;
-        for (uint32_t q = 0; q < sa.n; ++q) sa.d[q] = make_dev_desc(s[order[i0 + q]], order[i0 + q], tile[order[i0 + q]]);
+        for (uint32_t q = 0; q < sa.n; ++q) sa.d[q] = make_dev_desc(s[order[i0 + q]], order[i0 + q], tile[order[i0 + q]], c->lds_max);
         void *sargs[] = {&sa};
         HIP_TRY(c, hipLaunchKernel((const void *)&rsa_stage_descs, dim3(1), dim3(kStageDescs), sargs, 0, stream));
     }

@@ -37,6 +37,22 @@ __host__ __device__ inline uint32_t padded_words(uint32_t L) { return ((L + 63) 
 __host__ __device__ inline uint32_t padded_side(uint32_t L) { return (L + 31) & ~31u; }
 __host__ __device__ inline uint32_t summary_words(uint32_t L) { return (padded_words(L) + 63) / 64; }
 
+// Anchor intervals (the sparse clear of long k-mers).  On one line (a row of
+// H anchors, a column of V anchors) the available anchors are the intervals
+// [a, b-k+1] of the empty runs [a, b] of length >= k; two of them start at
+// least k+1 apart, so cut into buckets of k+1 positions the line holds at
+// most one piece of an interval per bucket, ceil(L/(k+1)) buckets per line.
+// A bucket entry is start | end << 16, or kNoSeg.
+constexpr uint32_t kNoSeg = 0xFFFFFFFFu;
+constexpr uint32_t kMaxBuckets = 64;       // one wave reads a whole line
+constexpr uint32_t kIntervalMaxK = 4096;   // difference counts of a k-row block in LDS
+__host__ __device__ inline uint32_t num_buckets(uint32_t L, uint32_t k) { return (L + k) / (k + 1); }
+__host__ __device__ inline bool has_buckets(uint32_t L, uint32_t k) { return num_buckets(L, k) <= kMaxBuckets; }
+// LDS after the common layout for the interval clear: per-row difference
+// counts of a k-row block, and their sums over 64 rows.
+__host__ __device__ inline uint32_t interval_diff_words(uint32_t k) { return (k + 1 + 3) & ~3u; }
+__host__ __device__ inline uint32_t interval_lds_bytes(uint32_t k) { return 4 * (interval_diff_words(k) + 68); }
+
 // One sample as the kernels see it.
 struct DevDesc {
     uint32_t L, k;
@@ -48,14 +64,15 @@ struct DevDesc {
     uint32_t lg_mr;    // site-map tile: 2^lg_mr rows x 2^(5-lg_mr) sites (128 B)
     uint32_t spec_rows;   // rows read ahead of each clear (power of two)
     uint32_t tile;        // schedule id reported in the result
-    uint32_t sparse;      // clear mode: 0 dense, 1 sparse (summary bits)
-    uint32_t pad1;
+    uint32_t sparse;      // clear mode: 0 dense, 1 sparse (summary bits or intervals)
+    uint32_t interval;    // sparse mode by anchor intervals (1) or by summary bits (0)
     uint64_t slab;        // the sample's own slab, or 0 = the workgroup's slab
     FastDiv fL;        // division by L
     FastDiv fk;        // division by k
     FastDiv fC;        // division by 2k+2 (contacts per k-mer)
     FastDiv fwd;       // division by wd
     FastDiv fwp;       // division by the padded row words
+    FastDiv fB;        // division by k+1 (interval bucket width)
 };
 
 // Mirrors rsa_result_t of include/rsa.h (104 bytes).
@@ -127,8 +144,11 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t L)
 //                       of row y may be non-zero (used by the sparse clear)
 //   state               SampleState, then the LDS row counts of a sample
 //                       that yielded (time-sliced runs only)
+//   hb, vb              anchor-interval buckets of H rows / V columns (when
+//                       has_buckets), bucket-major: entry j of line q at
+//                       [j * padded_side + q]
 struct SlabLayout {
-    size_t avail0, avail1, sum0, sum1, map, node, kmer, state, total;
+    size_t avail0, avail1, sum0, sum1, map, node, kmer, state, hb, vb, total;
 };
 
 // Status values of a time-sliced run besides 0 and the negative errors:
@@ -184,6 +204,9 @@ __host__ __device__ inline SlabLayout slab_layout(uint32_t L, uint32_t k)
     s.node = off;   off = align256(off + cap * 16);
     s.kmer = off;   off = align256(off + cap * 4);
     s.state = off;  off = align256(off + kStateBytes + lds_count_bytes(L));
+    const size_t nb = has_buckets(L, k) ? (size_t)num_buckets(L, k) * lp * 4 : 0;
+    s.hb = off;     off = align256(off + nb);
+    s.vb = off;     off = align256(off + nb);
     s.total = off;
     return s;
 }

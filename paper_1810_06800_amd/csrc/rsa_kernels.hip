@@ -197,6 +197,8 @@ struct Hdr {
     uint32_t stop;           // selection ends before this step (0 = at jamming)
     unsigned long long ncon[3];   // contact census: both H, both V, perpendicular
     unsigned long long sel_acc[7];   // selecting wave's phase counters (profiling)
+    uint32_t bar;            // interval clear: arrivals of the selecting waves at the mid-step barrier
+    uint32_t jrs, jn;        // interval clear: V anchors a vertical deposit removed from its own column
 };
 
 // Selecting-wave profile accumulators, kept in LDS rather than in registers.
@@ -224,6 +226,13 @@ struct Ctx {
     uint32_t *e_step;   // edge lists: step, then ms, vx, vy (kEdges each)
     uint32_t *s_par;    // local union-find: parent, then meta, gid, dx, dy (kSlots each)
     uint32_t *h_key;    // root hash: keys, then values (kHash each)
+    // interval clear (long k-mers): anchor-interval buckets of H rows and V
+    // columns in the slab, per-row difference counts of a block and their
+    // 64-row sums in LDS
+    uint32_t interval;
+    uint32_t *hb, *vb;
+    uint32_t *dD, *dC;
+    FastDiv fB;
 
     __device__ __forceinline__ uint32_t L2() const { return L * L; }
     __device__ __forceinline__ uint32_t wp() const { return padded_words(L); }
@@ -631,6 +640,405 @@ __device__ __forceinline__ void sparse_clear(const Ctx &c, const Clear &cl, uint
     sparse_rect<4, 8>(c, cl.b, wv, nwv, wchg);
 }
 
+// ---------------------------------------------------------------------------
+// Interval clear (long k-mers)
+// ---------------------------------------------------------------------------
+// A deposit makes unavailable every placement covering one of its sites
+// (Sec. II.B).  On one line (a row of H anchors or a column of V anchors)
+// those are the available anchors inside one cyclic range: the deposit's own
+// line loses [x-k+1, x+k-1] (its strip), each of the k lines it crosses loses
+// [x-k+1, x] (its row or column of the block).  A line's available anchors
+// live in buckets of k+1 positions, one interval piece each at most, so a
+// line's cut reads the two to four bucket entries its range touches and
+// writes back those that change: the k+1 lines of a deposit are cut side by
+// side in one round trip, with exact counts and without reading a bitmap.
+// V anchors are also kept in the row-major bitmap the select reads (within a
+// V row the canonical order runs across the columns); H rows are selected
+// from their buckets.
+
+// Result of cutting one line.
+struct LineCut {
+    uint32_t n;       // anchors removed
+    uint32_t nw;      // 64-bit words of the line's canonical bitmap row holding them
+    uint32_t start;   // first removed anchor in cyclic order (when n > 0)
+    bool bad;         // a bucket would keep two pieces: broken invariant
+};
+
+__device__ __forceinline__ uint32_t seg_start(uint32_t v) { return v & 0xFFFFu; }
+__device__ __forceinline__ uint32_t seg_end(uint32_t v) { return v >> 16; }
+
+// Remove the available anchors inside the cyclic range [lo, lo + len)
+// (len >= L: the whole line) from line q of `list`.  Lanes with `act` cut
+// their own line; every touched bucket keeps what lies outside the range.
+__device__ __forceinline__ LineCut cut_line(const Ctx &c, uint32_t *list, uint32_t q, uint32_t lo, uint32_t len,
+                                            bool act)
+{
+    const uint32_t L = c.L, lp = c.lp();
+    LineCut r;
+    r.n = 0;
+    r.nw = 0;
+    r.start = 0;
+    r.bad = false;
+    const bool full = len >= L;
+    const bool wraps = !full && lo + len > L;
+    const uint32_t wend = wraps ? lo + len - L : 0;   // the range's part past the seam: [0, wend)
+    // touched buckets, increasing (at most four: a range shorter than two
+    // buckets, split at most once by the seam)
+    uint32_t jv[4];
+    uint32_t nj = 0;
+    uint32_t ja, jb;
+    bool over = false;
+    if (full) {
+        ja = 0;
+        jb = fdiv(L - 1, c.fB);
+    } else if (wraps) {
+        const uint32_t jw = fdiv(wend - 1, c.fB);
+        for (uint32_t j = 0; j <= jw; ++j) {
+            if (nj == 4) {
+                over = true;
+                break;
+            }
+            jv[nj++] = j;
+        }
+        const uint32_t j0 = fdiv(lo, c.fB);
+        ja = j0 > jw + 1 ? j0 : jw + 1;
+        jb = fdiv(L - 1, c.fB);
+    } else {
+        ja = fdiv(lo, c.fB);
+        jb = fdiv(lo + len - 1, c.fB);
+    }
+    for (uint32_t j = ja; j <= jb; ++j) {
+        if (nj == 4) {
+            over = true;
+            break;
+        }
+        jv[nj++] = j;
+    }
+    r.bad = act && over;
+    uint32_t ev[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ev[i] = (act && (uint32_t)i < nj) ? list[jv[i] * lp + q] : kNoSeg;
+    int32_t lastw = -1;
+    uint32_t prev_e = 0;
+    bool first = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t E = ev[i];
+        if (E == kNoSeg) continue;
+        const int32_t s = (int32_t)seg_start(E), e = (int32_t)seg_end(E);
+        // the part of the piece outside the range stays (one interval at most)
+        int32_t ks = 1, ke = 0;
+        if (!full) {
+            if (wraps) {   // outside: [wend, lo)
+                const int32_t a = s > (int32_t)wend ? s : (int32_t)wend;
+                const int32_t b = e < (int32_t)lo - 1 ? e : (int32_t)lo - 1;
+                if (a <= b) {
+                    ks = a;
+                    ke = b;
+                }
+            } else {       // outside: [lo + len, L) and [0, lo)
+                const int32_t ca = (int32_t)(lo + len);
+                const int32_t a1 = s > ca ? s : ca;
+                const int32_t b2 = e < (int32_t)lo - 1 ? e : (int32_t)lo - 1;
+                const bool k1 = a1 <= e;
+                const bool k2 = s <= b2;
+                if (k1 && k2) r.bad = true;
+                if (k1) {
+                    ks = a1;
+                    ke = e;
+                } else if (k2) {
+                    ks = s;
+                    ke = b2;
+                }
+            }
+        }
+        const bool keep = ks <= ke;
+        // removed pieces, in increasing position
+        int32_t ps0 = s, pe0 = e, ps1 = 0, pe1 = -1;
+        if (keep) {
+            pe0 = ks - 1;          // left of what stays (empty if ks == s)
+            ps1 = ke + 1;          // right of it (empty if ke == e)
+            pe1 = e;
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int32_t a = p ? ps1 : ps0, b = p ? pe1 : pe0;
+            if (a > b) continue;
+            r.n += (uint32_t)(b - a + 1);
+            int32_t w0 = a >> 6;
+            const int32_t w1 = b >> 6;
+            if (w0 <= lastw) w0 = lastw + 1;
+            if (w1 >= w0) r.nw += (uint32_t)(w1 - w0 + 1);
+            if (w1 > lastw) lastw = w1;
+            // the cyclic start follows the gap between two removed pieces,
+            // if there is one; otherwise it is the first piece
+            if (first || (uint32_t)a != prev_e + 1) r.start = (uint32_t)a;
+            first = false;
+            prev_e = (uint32_t)b;
+        }
+        const uint32_t nv = keep ? ((uint32_t)ks | ((uint32_t)ke << 16)) : kNoSeg;
+        if (nv != E) list[jv[i] * lp + q] = nv;
+    }
+    return r;
+}
+
+// Wave-wide minimum / maximum / OR.
+__device__ __forceinline__ uint32_t wave_min32(uint32_t v)
+{
+#pragma unroll
+    for (uint32_t d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, (int)d, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max32(uint32_t v)
+{
+#pragma unroll
+    for (uint32_t d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, (int)d, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_or32(uint32_t v)
+{
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return bcast(v, 63);
+}
+
+// Bits a..b (0 <= a, b <= 63) of a word, or 0 when a > b.
+__device__ __forceinline__ uint64_t bit_range(int32_t a, int32_t b)
+{
+    if (a > b) return 0;
+    return (~0ull >> (63 - b)) & (~0ull << a);
+}
+
+// Subtract v from the count of canonical row R for every lane with `act`:
+// the row counts lane by lane, their 64-row and 4096-row sums once per
+// distinct 64-row group of the wave.
+__device__ __forceinline__ void count_sub_wave(const Ctx &c, bool act, uint32_t R, uint32_t v)
+{
+    const bool on = act && v != 0;
+    if (on) atomicSub(&c.cnt0[R >> 1], v << ((R & 1) << 4));
+    uint64_t pend = __ballot(on);
+    while (pend) {
+        const uint32_t g = bcast(R >> 6, first_lane(pend));
+        const bool in = on && (R >> 6) == g;
+        const uint32_t sum = wave_sum32(in ? v : 0u);
+        if (lane_id() == 0) {
+            atomicSub(&c.cnt1[g], sum);
+            atomicSub(&c.cnt2[g >> 6], sum);
+        }
+        pend &= ~__ballot(in);
+    }
+}
+
+// The selecting waves meet once per step between the two phases of the
+// interval clear (LDS arrivals counter; every wave passes the same number).
+template <int NSEL>
+__device__ __forceinline__ void sel_barrier(const Ctx &c, uint32_t &passed)
+{
+    if constexpr (NSEL > 1) {
+        ++passed;
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (lane_id() == 0) atomicAdd(&c.h->bar, 1u);
+        while (lds_load(&c.h->bar) < passed * (uint32_t)NSEL) __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Aligned 64-blocks of line indices covering the cyclic span [q0, q0 + k):
+// the part past the seam [0, q0 + k - L) first, then [q0, ...); a block both
+// parts touch is listed once.
+struct Span {
+    uint32_t q0, k;
+    uint32_t e2;       // blocks 0 .. e2 - 1 come from the part past the seam
+    uint32_t s1, n;    // then blocks s1, s1 + 1, ...; n blocks in all
+};
+
+__device__ __forceinline__ Span make_span(const Ctx &c, uint32_t q0, uint32_t k)
+{
+    const uint32_t L = c.L;
+    Span sp;
+    sp.q0 = q0;
+    sp.k = k;
+    const uint32_t end1 = q0 + k < L ? q0 + k : L;
+    const uint32_t b1 = q0 >> 6, l1 = (end1 - 1) >> 6;
+    if (q0 + k > L) {
+        const uint32_t l2 = (q0 + k - L - 1) >> 6;
+        sp.e2 = l2 + 1;
+        sp.s1 = b1 > l2 ? b1 : l2 + 1;
+        sp.n = sp.e2 + (l1 >= sp.s1 ? l1 - sp.s1 + 1 : 0);
+    } else {
+        sp.e2 = 0;
+        sp.s1 = b1;
+        sp.n = l1 - b1 + 1;
+    }
+    return sp;
+}
+
+__device__ __forceinline__ uint32_t span_block(const Span &sp, uint32_t m)
+{
+    return m < sp.e2 ? m : sp.s1 + (m - sp.e2);
+}
+
+__device__ __forceinline__ bool in_span(const Ctx &c, const Span &sp, uint32_t q)
+{
+    if (q >= c.L) return false;
+    uint32_t d = q + c.L - sp.q0;
+    d = d >= c.L ? d - c.L : d;
+    return d < sp.k;
+}
+
+// Wave wv of NSEL clears its share of the deposit (o, y, x): phase one cuts
+// the lines (the selecting wave also the deposit's own line), phase two
+// turns the block's cuts into row counts; the selecting waves meet between.
+template <int NSEL>
+__device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_t y, uint32_t x, uint32_t wv,
+                                               uint32_t &wchg, uint32_t &passed)
+{
+    const uint32_t L = c.L, k = c.k, lane = lane_id();
+    const uint32_t strip = 2 * k - 1 < L ? 2 * k - 1 : L;
+    uint32_t xb = x + L - (k - 1);
+    xb = xb >= L ? xb - L : xb;
+    uint32_t yb = y + L - (k - 1);
+    yb = yb >= L ? yb - L : yb;
+    bool bad = false;
+    // ---- phase one
+    if (wv == 0) {
+        // the deposit's own line: H row y loses [x-k+1, x+k-1], V column x
+        // loses [y-k+1, y+k-1]
+        const LineCut cut = cut_line(c, o ? c.vb : c.hb, o ? x : y, o ? yb : xb, strip, lane == 0);
+        bad = bad || cut.bad;
+        if (lane == 0) {
+            if (o == 0) {
+                if (cut.n) count_sub(c, y, cut.n);
+                wchg += cut.nw;
+            } else {
+                c.h->jrs = cut.start;
+                c.h->jn = cut.n;
+                wchg += cut.n;   // one V word per row of the column
+            }
+        }
+    }
+    // the crossing lines: for H, V columns x .. x+k-1 lose rows [y-k+1, y];
+    // for V, H rows y .. y+k-1 lose columns [x-k+1, x]
+    const Span sp = make_span(c, o ? y : x, k);
+    uint32_t *const blist = o ? c.hb : c.vb;
+    const uint32_t blo = o ? xb : yb;
+    for (uint32_t m = wv; m < sp.n; m += NSEL) {
+        const uint32_t blk = span_block(sp, m);
+        const uint32_t q = blk * 64 + lane;
+        const bool act = in_span(c, sp, q);
+        const LineCut cut = cut_line(c, blist, q, blo, k, act);
+        bad = bad || cut.bad;
+        if (o == 1) {
+            // H row q: its count drops by the anchors removed
+            count_sub_wave(c, act, q, cut.n);
+            wchg += cut.nw;
+            continue;
+        }
+        // V column q: rows blo + [l, h] (block-relative, h < k) lose an anchor
+        const bool has = act && cut.n != 0;
+        uint32_t l = 0;
+        if (has && cut.n < k) {
+            l = cut.start + L - blo;
+            l = l >= L ? l - L : l;
+        }
+        const uint32_t h = l + cut.n - 1;
+        // a cut lies inside the block's k rows; anything else is a broken
+        // invariant and is reported, never written
+        const bool in_block = h < k;
+        bad = bad || (has && !in_block);
+        const bool has_ok = has && in_block;
+        if (has_ok) {
+            atomicAdd(&c.dD[l], 1u);
+            atomicAdd(&c.dC[l >> 6], 1u);
+            if (h + 1 < k) {
+                atomicSub(&c.dD[h + 1], 1u);
+                atomicSub(&c.dC[(h + 1) >> 6], 1u);
+            }
+        }
+        // the row-major V bitmap: word blk of every row where some column of
+        // it lost an anchor; the span's bits of it become 0
+        const uint64_t anyh = __ballot(has_ok);
+        if (anyh == 0) continue;
+        const uint64_t spanmask = __ballot(act);
+        const bool whole = spanmask == ~0ull;
+        const uint32_t fl = first_lane(anyh);
+        const uint32_t l0 = bcast(l, fl), h0 = bcast(h, fl);
+        const bool same = __ballot(has_ok && (l != l0 || h != h0)) == 0;
+        const uint32_t lmin = same ? l0 : wave_min32(has_ok ? l : 0xFFFFFFFFu);
+        const uint32_t hmax = same ? h0 : wave_max32(has_ok ? h : 0u);
+        uint64_t *const bm = c.av1;
+        for (uint32_t g = lmin >> 6; g <= (hmax >> 6); ++g) {
+            const int32_t base = (int32_t)(g * 64);
+            uint64_t U;
+            if (same) {
+                U = bit_range((int32_t)l0 > base ? (int32_t)l0 - base : 0,
+                              (int32_t)h0 < base + 63 ? (int32_t)h0 - base : 63);
+            } else {
+                const uint64_t mine = has_ok ? bit_range((int32_t)l > base ? (int32_t)l - base : 0,
+                                                         (int32_t)h < base + 63 ? (int32_t)h - base : 63)
+                                             : 0ull;
+                U = (uint64_t)wave_or32((uint32_t)mine) | ((uint64_t)wave_or32((uint32_t)(mine >> 32)) << 32);
+            }
+            if ((U >> lane) & 1ull) {
+                uint32_t row = blo + (uint32_t)base + lane;
+                row = row >= L ? row - L : row;
+                const uint32_t at = bm_index(c, row, blk);
+                if (whole)
+                    bm[at] = 0ull;
+                else
+                    atomicAnd((unsigned long long *)&bm[at], (unsigned long long)~spanmask);
+            }
+            if (lane == 0) wchg += (uint32_t)__popcll(U);
+        }
+    }
+    if (__ballot(bad) && lane == 0) c.h->status = kErrSelect;
+    sel_barrier<NSEL>(c, passed);
+    // ---- phase two
+    if (o == 0) {
+        // V rows blo + i, i < k: the counts drop by the number of columns
+        // whose cut covers row i (difference counts, their 64-row sums give
+        // each block's carry)
+        const uint32_t nC = (k + 63) >> 6;   // <= 64
+        const uint32_t cv = lane < nC ? lds_peek(&c.dC[lane]) : 0u;
+        const uint32_t cinc = wave_scan(cv);
+        const uint32_t cex = cinc - cv;
+        for (uint32_t m = wv; m < nC; m += NSEL) {
+            const uint32_t i = m * 64 + lane;
+            const bool act = i < k;
+            const uint32_t dv = act ? lds_peek(&c.dD[i]) : 0u;
+            if (act) c.dD[i] = 0u;
+            const uint32_t dcount = wave_scan(dv) + bcast(cex, m);
+            uint32_t row = blo + i;
+            row = row >= L ? row - L : row;
+            count_sub_wave(c, act, L + row, dcount);
+        }
+    } else {
+        // V rows of the deposit's own column that lost their anchor at x
+        const uint32_t jrs = lds_peek(&c.h->jrs), jn = lds_peek(&c.h->jn);
+        uint64_t *const bm = c.av1;
+        const uint64_t bit = 1ull << (x & 63u);
+        for (uint32_t m = wv; m * 64 < jn; m += NSEL) {
+            const uint32_t i = m * 64 + lane;
+            const bool act = i < jn;
+            uint32_t row = jrs + i;
+            row = row >= L ? row - L : row;
+            count_sub_wave(c, act, L + row, 1u);
+            if (act) atomicAnd((unsigned long long *)&bm[bm_index(c, row, x >> 6)], (unsigned long long)~bit);
+        }
+    }
+}
+
 // Words a lane holds of one bitmap row: lane, lane+64, ... (ROWW of them;
 // ROWW = 1 covers L <= 4096, 8 covers L <= 32768).
 template <int ROWW>
@@ -865,6 +1273,31 @@ __device__ __forceinline__ void row_from_window(const Ctx &c, const SpecRows<SPW
     }
 }
 
+// The rin-th available placement of row R (canonical index in P): for H
+// rows under the interval clear from the row's buckets (one entry per lane,
+// in position order), otherwise from the row's bitmap words.
+template <int ROWW>
+__device__ __forceinline__ bool pick_row(const Ctx &c, uint32_t R, uint32_t rin, uint32_t &P)
+{
+    if (c.interval && R < c.L) {
+        const uint32_t lane = lane_id();
+        const uint32_t nS = num_buckets(c.L, c.k);
+        const uint32_t E = lane < nS ? c.hb[lane * c.lp() + R] : kNoSeg;
+        const uint32_t len = E == kNoSeg ? 0u : seg_end(E) - seg_start(E) + 1;
+        const uint32_t inc = wave_scan(len);
+        const uint64_t bal = __ballot(inc > rin);
+        if (bal == 0) return false;
+        const uint32_t j = first_lane(bal);
+        const uint32_t x = bcast(seg_start(E), j) + (rin - bcast(inc - len, j));
+        if (x >= c.L) return false;
+        P = uniform(R * c.L + x);
+        return true;
+    }
+    RowWords<ROWW> rw;
+    load_row(c, R, rw);
+    return pick_in_row(c, rw, R, rin, P);
+}
+
 template <int NSEL>
 struct TileCap {
     static constexpr int value = NSEL == 1 ? 4 : 8;
@@ -902,16 +1335,13 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
     uint32_t t = t_begin;
     uint32_t P = c.h->p0;
     bool alive = true, yielded = false;
+    uint32_t passed = 0;   // mid-step barriers of the interval clear
     if (!c.h->resumed) {   // first placement
         uint32_t inc2, v2, R, rin;
         uint32_t A = scan_top(c, inc2, v2);
         uint32_t r = uniform(draw_rank(bcast64(u_pre, 0), A));
-        RowWords<ROWW> rw;
         alive = A > 0 && locate_row(c, inc2, v2, r, R, rin);
-        if (alive) {
-            load_row(c, R, rw);
-            alive = pick_in_row(c, rw, R, rin, P);
-        }
+        if (alive) alive = pick_row<ROWW>(c, R, rin, P);
         if (!alive && A > 0 && lane == 0) c.h->status = kErrSelect;
     }
     while (alive) {
@@ -979,18 +1409,24 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         sp.o = sp.y0 = sp.nr = 0;
         uint64_t ph = prof ? tick() : 0;
         if constexpr (SPARSE) {
-            if constexpr (SPW > 0) {
-                plan_ahead<SPW>(c, cl, u1, inv2l2, sp);
-                load_ahead<SPW>(c, sp);
+            if (c.interval) {
+                hash_step();
+                interval_clear<NSEL>(c, o, y, x, 0, wchg, passed);
+                if (prof && lane == 0) acc[kAccProcess] += tick() - ph;
+            } else {
+                if constexpr (SPW > 0) {
+                    plan_ahead<SPW>(c, cl, u1, inv2l2, sp);
+                    load_ahead<SPW>(c, sp);
+                }
+                if (prof) {
+                    uint64_t ph1 = tick();
+                    if (lane == 0) acc[kAccHook] += ph1 - ph;
+                    ph = ph1;
+                }
+                hash_step();
+                sparse_clear<CAP>(c, cl, 0, NSEL, wchg);
+                if (prof && lane == 0) acc[kAccProcess] += tick() - ph;
             }
-            if (prof) {
-                uint64_t ph1 = tick();
-                if (lane == 0) acc[kAccHook] += ph1 - ph;
-                ph = ph1;
-            }
-            hash_step();
-            sparse_clear<CAP>(c, cl, 0, NSEL, wchg);
-            if (prof && lane == 0) acc[kAccProcess] += tick() - ph;
         } else {
             const auto hook = [&] {
                 hash_step();
@@ -1008,6 +1444,10 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
             while (lds_load(&c.h->clr_done) < want) __builtin_amdgcn_s_sleep(1);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
+        if (SPARSE && c.interval && o == 0) {
+            // every wave is past this step's block sums: clear them for the next
+            if (lane < ((k + 63) >> 6)) c.dC[lane] = 0u;
+        }
         if (prof) {
             uint64_t p1 = tick();
             if (lane == 0) acc[kAccClear] += p1 - p0;
@@ -1022,18 +1462,25 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
             if (lane == 0) c.h->status = kErrSelect;
             break;
         }
-        RowWords<ROWW> rw;
-        const uint32_t ro = R >= L ? 1u : 0u, ry = R - ro * L;
-        if (SPW > 0 && sp.nr && ro == sp.o && ry >= sp.y0 && ry < sp.y0 + sp.nr) {
-            row_from_window<SPW == 0 ? 1 : SPW, ROWW>(c, sp, ry, rw);
-            patch_row(c, cl, R, rw);
-            if (prof && lane == 0) ++acc[kAccSpec];
+        if (SPARSE && c.interval) {
+            if (!pick_row<ROWW>(c, R, rin, P)) {
+                if (lane == 0) c.h->status = kErrSelect;
+                break;
+            }
         } else {
-            load_row(c, R, rw);
-        }
-        if (!pick_in_row(c, rw, R, rin, P)) {
-            if (lane == 0) c.h->status = kErrSelect;
-            break;
+            RowWords<ROWW> rw;
+            const uint32_t ro = R >= L ? 1u : 0u, ry = R - ro * L;
+            if (SPW > 0 && sp.nr && ro == sp.o && ry >= sp.y0 && ry < sp.y0 + sp.nr) {
+                row_from_window<SPW == 0 ? 1 : SPW, ROWW>(c, sp, ry, rw);
+                patch_row(c, cl, R, rw);
+                if (prof && lane == 0) ++acc[kAccSpec];
+            } else {
+                load_row(c, R, rw);
+            }
+            if (!pick_in_row(c, rw, R, rin, P)) {
+                if (lane == 0) c.h->status = kErrSelect;
+                break;
+            }
         }
         if (prof && lane == 0) acc[kAccSelect] += tick() - p0;
     }
@@ -1068,6 +1515,7 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
     const uint32_t lane = lane_id();
     __builtin_amdgcn_s_setprio(2);
     uint32_t wchg = 0;
+    uint32_t passed = 0;    // mid-step barriers of the interval clear
     uint32_t g = c.h->t0;   // clear requests are numbered by step
     for (;;) {
         uint32_t gen;
@@ -1088,11 +1536,14 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
         uint32_t rem = P - o * c.L2();
         uint32_t y = fdiv(rem, c.fL);
         uint32_t x = rem - y * c.L;
-        const Clear cl = make_clear(c, o, y, x);
-        if constexpr (SPARSE)
-            sparse_clear<CAP>(c, cl, wv, NSEL, wchg);
-        else
-            clear_items<CAP, ROWW == 1>(c, cl, wv, NSEL, wchg);
+        if constexpr (SPARSE) {
+            if (c.interval)
+                interval_clear<NSEL>(c, o, y, x, wv, wchg, passed);
+            else
+                sparse_clear<CAP>(c, make_clear(c, o, y, x), wv, NSEL, wchg);
+        } else {
+            clear_items<CAP, ROWW == 1>(c, make_clear(c, o, y, x), wv, NSEL, wchg);
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (lane == 0) atomicAdd(&c.h->clr_done, 1u);
     }
@@ -1783,6 +2234,12 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
     c.e_step = (uint32_t *)(lds + l.edges);
     c.s_par = (uint32_t *)(lds + l.slots);
     c.h_key = (uint32_t *)(lds + l.hash);
+    c.interval = d.interval;
+    c.hb = (uint32_t *)(slab + s.hb);
+    c.vb = (uint32_t *)(slab + s.vb);
+    c.dD = (uint32_t *)(lds + l.total);
+    c.dC = c.dD + interval_diff_words(d.k);
+    c.fB = d.fB;
 }
 
 // One sample on one workgroup.  deadline = 0 runs it from the empty lattice
@@ -1870,14 +2327,27 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
         const uint32_t tailbits = L & 63u;
         const uint64_t last = tailbits ? ((1ull << tailbits) - 1) : ~0ull;
         const uint32_t nwords = c.lp() * c.wp();
+        const bool iv = SPARSE && c.interval;
         for (uint32_t i = tid; i < nwords; i += NT) {
             uint32_t row = fdiv(i, c.fwp), wi = i - row * c.wp();
             uint64_t full = (row >= L || wi >= wd) ? 0ull : (wi == wd - 1 ? last : ~0ull);
             const uint32_t at = bm_index(c, row, wi);
-            c.av0[at] = full;
+            if (!iv) c.av0[at] = full;   // the interval clear keeps H anchors in buckets only
             c.av1[at] = h_only ? 0ull : full;
         }
-        if (SPARSE) {
+        if (iv) {
+            // every line one run: bucket j holds [j(k+1), min((j+1)(k+1), L) - 1]
+            const uint32_t nS = num_buckets(L, c.k), B = c.k + 1;
+            for (uint32_t j = 0; j < nS; ++j) {
+                const uint32_t a = j * B, b = (a + B < L ? a + B : L) - 1;
+                const uint32_t E = a | (b << 16);
+                for (uint32_t q = tid; q < L; q += NT) {
+                    c.hb[j * c.lp() + q] = E;
+                    c.vb[j * c.lp() + q] = h_only ? kNoSeg : E;
+                }
+            }
+        }
+        if (SPARSE && !iv) {
             // summary bit set for every word of a real row and column
             const uint32_t nsum = c.lp() * c.swp();
             for (uint32_t i = tid; i < nsum; i += NT) {
@@ -1934,6 +2404,10 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             for (int q = 0; q < 7; ++q) h->sel_acc[q] = 0;
         }
     }
+    if (SPARSE && c.interval) {
+        for (uint32_t i = tid; i < interval_diff_words(c.k) + 68; i += NT) c.dD[i] = 0u;
+    }
+    if (tid == 0) c.h->bar = 0;
     __syncthreads();
     if (c.prof && tid == 0) atomicAdd(&c.prof[kProfInit], (unsigned long long)(tick() - p_init));
 

@@ -135,8 +135,15 @@ void *take_pinned(rsa_ctx *c, size_t bytes);
 void give_pinned(rsa_ctx *c, void *p, size_t bytes);
 // Workgroups of a schedule's kernel resident on the whole device at once.
 int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, int census, uint32_t lds);
+// Whether a sample of a sparse-clear tile runs the interval clear: k up to
+// kIntervalMaxK, at most kMaxBuckets buckets per line, and its difference
+// counts fit the workgroup's LDS beside the row counts.  Otherwise the sparse
+// clear by summary bits.
+bool use_interval(uint32_t L, uint32_t k, int tile, size_t lds_max);
+// Dynamic LDS bytes the sample's kernel needs.
+uint32_t sample_lds(uint32_t L, uint32_t k, int tile, size_t lds_max);
 // Kernel-side descriptor of a sample; `out` is its index in the result array.
-DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile);
+DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile, size_t lds_max);
 
 }  // namespace rsa
 

@@ -94,7 +94,7 @@ struct rsa_server {
 
 namespace {
 
-uint32_t lds_bytes(uint32_t L) { return lds_layout(L).total; }
+uint32_t lds_bytes(const rsa_ctx *c, const rsa_sample_t &s, int tile) { return sample_lds(s.L, s.k, tile, c->lds_max); }
 
 // Kernel group of a sample: (waves, rows wider than 64 words, sparse clear,
 // contact census) select the kernel; the last bit splits lattices up to
@@ -222,7 +222,7 @@ int launch(rsa_server *v)
     const uint32_t n = (uint32_t)live.size();
     for (uint32_t i = 0; i < n; ++i) {
         Sample &sm = v->samples[live[i]];
-        DevDesc d = make_dev_desc(sm.s, i, sm.tile);
+        DevDesc d = make_dev_desc(sm.s, i, sm.tile, c->lds_max);
         d.slab = (uint64_t)(uintptr_t)(v->arena_base + sm.off);
         if (!sm.listed) d.flags |= kDescFresh;
         sm.listed = true;
@@ -241,7 +241,7 @@ int launch(rsa_server *v)
         const int key = v->samples[live[i]].key;
         uint32_t j = i, lds = 0;
         while (j < n && v->samples[live[j]].key == key) {
-            lds = std::max(lds, lds_bytes(v->samples[live[j]].s.L));
+            lds = std::max(lds, lds_bytes(c, v->samples[live[j]].s, v->samples[live[j]].tile));
             ++j;
         }
         const int kern = key >> 1;
@@ -394,7 +394,7 @@ int rsa_server_submit(rsa_server *v, const rsa_sample_t *s, uint32_t n, uint64_t
             return fail(c, RSA_EINVAL, "invalid descriptor at index " + std::to_string(i));
         if (s[i].flags & RSA_FLAG_CLUSTER_SIZES)
             return fail(c, RSA_EINVAL, "cluster sizes are a batch feature (rsa_batch_cluster_sizes)");
-        if (lds_bytes(s[i].L) + 64 > c->lds_max) return fail(c, RSA_EINVAL, "lattice too large for LDS");
+        if (lds_layout(s[i].L).total + 64 > c->lds_max) return fail(c, RSA_EINVAL, "lattice too large for LDS");
         if (Arena::round(slab_layout(s[i].L, s[i].k).total) > v->arena.size())
             return fail(c, RSA_ENOMEM, "sample larger than the server arena");
     }

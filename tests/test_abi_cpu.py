@@ -48,7 +48,9 @@ def test_footprint_matches_layout(rsa):
     # every area 256-byte aligned
     # (rows and columns padded so that every 128-byte tile shape fits),
     # plus a 256-byte state record and room for the 2L uint16 row counts and
-    # their sums over 64 and 4096 rows (time-sliced runs)
+    # their sums over 64 and 4096 rows (time-sliced runs), and when a line has
+    # at most 64 buckets of k+1 positions, the anchor-interval buckets of the
+    # H rows and of the V columns (4 B per bucket and line)
     def expect(L, k):
         a = lambda v: (v + 255) // 256 * 256
         r16 = lambda v: (v + 15) // 16 * 16
@@ -58,10 +60,13 @@ def test_footprint_matches_layout(rsa):
         summary = a(lp * ((wp + 63) // 64) * 8)
         rows = 2 * L
         counts = r16((rows + 1) // 2 * 4) + r16((rows + 63) // 64 * 4) + r16((rows + 4095) // 4096 * 4)
+        nb = (L + k) // (k + 1)
+        buckets = 2 * a(4 * nb * lp) if nb <= 64 else 0
         return (a(lp * wp * 8) * 2 + summary * 2 + a(4 * lp * lp) + a(16 * cap) + a(4 * cap)
-                + a(256 + counts))
+                + a(256 + counts) + buckets)
 
-    for L, k in [(1, 1), (5, 3), (64, 8), (1024, 64), (16384, 1024), (32768, 4096)]:
+    for L, k in [(1, 1), (5, 3), (64, 8), (1024, 64), (16384, 1024), (32768, 4096), (16384, 2),
+                 (130, 1), (4096, 63)]:
         assert rsa.footprint_bytes(L, k) == expect(L, k)
     assert rsa.footprint_bytes(1024, 64) < 5 * 2**20
     assert 4.2 * 2**30 < rsa.footprint_bytes(32768, 4096) < 4.4 * 2**30
