@@ -220,6 +220,14 @@ bool use_interval(uint32_t L, uint32_t k, int tile, size_t lds_max)
            (size_t)lds_layout(L).total + interval_lds_bytes(k) + 64 <= lds_max;
 }
 
+bool use_compressed(uint32_t L, uint32_t k, int tile)
+{
+    (void)L;
+    return tile_sparse(tile) && k >= kCompressMinK;
+}
+
+size_t sample_slab(uint32_t L, uint32_t k, int tile) { return slab_layout(L, k, use_compressed(L, k, tile)).total; }
+
 uint32_t sample_lds(uint32_t L, uint32_t k, int tile, size_t lds_max)
 {
     return lds_layout(L).total + (use_interval(L, k, tile, lds_max) ? interval_lds_bytes(k) : 0u);
@@ -243,6 +251,7 @@ DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile, size_t lds_
     d.fwp = make_fastdiv(padded_words(s.L));
     d.fB = make_fastdiv(s.k + 1);
     d.interval = use_interval(s.L, s.k, tile, lds_max) ? 1u : 0u;
+    d.compressed = use_compressed(s.L, s.k, tile) ? 1u : 0u;
     d.tile = (uint32_t)tile;
     d.sparse = (uint32_t)tile_sparse(tile);
     d.lg_tr = (uint32_t)tile_lg_tr(tile);
@@ -304,7 +313,7 @@ const char *rsa_last_error(rsa_ctx *ctx) { return ctx ? ctx->last_error.c_str() 
 size_t rsa_footprint_bytes(uint32_t L, uint32_t k)
 {
     if (k < 1 || k > L || L > 32768) return 0;
-    return slab_layout(L, k).total;
+    return sample_slab(L, k, default_tile(L, k));
 }
 
 int rsa_num_tiles(void) { return kNumTiles; }
@@ -511,7 +520,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         uint32_t lds = 0;
         while (j < ne && keys[order[j]] == keys[order[i]] && ent_pass[order[j]] == ent_pass[order[i]]) {
             const rsa_sample_t &x = s[ent_sample[order[j]]];
-            stride = std::max(stride, slab_layout(x.L, x.k).total);
+            stride = std::max(stride, sample_slab(x.L, x.k, tiles[ent_sample[order[j]]]));
             lds = std::max(lds, sample_lds(x.L, x.k, tiles[ent_sample[order[j]]], c->lds_max));
             ++j;
         }
@@ -810,7 +819,7 @@ int rsa_run_batch_static(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, rsa_resu
         uint32_t lds = 0;
         while (j < n && key[order[j]] == key[order[i]]) {
             const rsa_sample_t &x = s[order[j]];
-            stride = std::max(stride, slab_layout(x.L, x.k).total);
+            stride = std::max(stride, sample_slab(x.L, x.k, tile[order[j]]));
             lds = std::max(lds, sample_lds(x.L, x.k, tile[order[j]], c->lds_max));
             ++j;
         }

@@ -48,6 +48,24 @@ constexpr uint32_t kMaxBuckets = 64;       // one wave reads a whole line
 constexpr uint32_t kIntervalMaxK = 4096;   // difference counts of a k-row block in LDS
 __host__ __device__ inline uint32_t num_buckets(uint32_t L, uint32_t k) { return (L + k) / (k + 1); }
 __host__ __device__ inline bool has_buckets(uint32_t L, uint32_t k) { return num_buckets(L, k) <= kMaxBuckets; }
+// Compressed lattice (Sec. II.E stores a few bits per site instead of the
+// cluster data): for long k-mers the int32 site map gives way to six bitmaps
+// of one bit per site -- occupied by an H k-mer, by a V k-mer, H anchor, V
+// anchor, the occupancies kept both along rows and along columns -- and an
+// open-addressing table from a k-mer's canonical placement index to its
+// deposit number.  Words hold 64 consecutive sites of one line; the copies
+// written across their lines are stored 16 lines to a 128-byte tile.
+constexpr uint32_t kCompressMinK = 512;
+__host__ __device__ inline uint32_t line_words(uint32_t L) { return (L + 63) / 64; }
+__host__ __device__ inline uint32_t tile16(uint32_t L) { return (L + 15) / 16; }
+__host__ __device__ inline uint32_t hash_slots(uint32_t L, uint32_t k)
+{
+    const uint64_t need = 2ull * ((uint64_t)L * L / k + 1);
+    uint32_t c = 64;
+    while (c < need) c <<= 1;
+    return c;
+}
+
 // LDS after the common layout for the interval clear: per-row difference
 // counts of a k-row block, and their sums over 64 rows.
 __host__ __device__ inline uint32_t interval_diff_words(uint32_t k) { return (k + 1 + 3) & ~3u; }
@@ -66,6 +84,8 @@ struct DevDesc {
     uint32_t tile;        // schedule id reported in the result
     uint32_t sparse;      // clear mode: 0 dense, 1 sparse (summary bits or intervals)
     uint32_t interval;    // sparse mode by anchor intervals (1) or by summary bits (0)
+    uint32_t compressed;  // site map replaced by occupancy / anchor bitmaps (1)
+    uint32_t pad2;
     uint64_t slab;        // the sample's own slab, or 0 = the workgroup's slab
     FastDiv fL;        // division by L
     FastDiv fk;        // division by k
@@ -147,8 +167,13 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t L)
 //   hb, vb              anchor-interval buckets of H rows / V columns (when
 //                       has_buckets), bucket-major: entry j of line q at
 //                       [j * padded_side + q]
+//   ohr, ovr, ohc, ovc  compressed lattice (instead of map): H / V occupancy
+//                       along rows (ovr tiled) and along columns (ohc tiled)
+//   ahr, avc            H anchors along rows, V anchors along columns
+//   khash               placement index + 1 | deposit number << 32, per slot
 struct SlabLayout {
-    size_t avail0, avail1, sum0, sum1, map, node, kmer, state, hb, vb, total;
+    size_t avail0, avail1, sum0, sum1, map, node, kmer, state, hb, vb;
+    size_t ohr, ovr, ohc, ovc, ahr, avc, khash, total;
 };
 
 // Status values of a time-sliced run besides 0 and the negative errors:
@@ -190,7 +215,7 @@ __host__ __device__ inline uint32_t lds_count_bytes(uint32_t L)
 
 __host__ __device__ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-__host__ __device__ inline SlabLayout slab_layout(uint32_t L, uint32_t k)
+__host__ __device__ inline SlabLayout slab_layout(uint32_t L, uint32_t k, bool compressed = false)
 {
     SlabLayout s;
     size_t wp = padded_words(L), lp = padded_side(L);
@@ -200,7 +225,16 @@ __host__ __device__ inline SlabLayout slab_layout(uint32_t L, uint32_t k)
     s.avail1 = off; off = align256(off + lp * wp * 8);
     s.sum0 = off;   off = align256(off + lp * summary_words(L) * 8);   // summary bits, see below
     s.sum1 = off;   off = align256(off + lp * summary_words(L) * 8);
-    s.map = off;    off = align256(off + lp * lp * 4);
+    s.map = off;    off = align256(off + (compressed ? 0 : lp * lp * 4));
+    const size_t bw = (size_t)line_words(L) * tile16(L) * 16 * 8;   // one bitmap (tiled or not)
+    const size_t nbm = compressed ? bw : 0;
+    s.ohr = off;    off = align256(off + nbm);
+    s.ovr = off;    off = align256(off + nbm);
+    s.ohc = off;    off = align256(off + nbm);
+    s.ovc = off;    off = align256(off + nbm);
+    s.ahr = off;    off = align256(off + nbm);
+    s.avc = off;    off = align256(off + nbm);
+    s.khash = off;  off = align256(off + (compressed ? (size_t)hash_slots(L, k) * 8 : 0));
     s.node = off;   off = align256(off + cap * 16);
     s.kmer = off;   off = align256(off + cap * 4);
     s.state = off;  off = align256(off + kStateBytes + lds_count_bytes(L));

@@ -233,6 +233,11 @@ struct Ctx {
     uint32_t *hb, *vb;
     uint32_t *dD, *dC;
     FastDiv fB;
+    // compressed lattice (long k-mers): occupancy and anchor bitmaps and the
+    // placement -> deposit table instead of the site map
+    uint32_t compressed, nlw, nt16, hlg;
+    uint64_t *ohr, *ovr, *ohc, *ovc, *ahr, *avc;
+    unsigned long long *khash;
 
     __device__ __forceinline__ uint32_t L2() const { return L * L; }
     __device__ __forceinline__ uint32_t wp() const { return padded_words(L); }
@@ -1552,6 +1557,284 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
 }
 
 // ---------------------------------------------------------------------------
+// Compressed lattice (long k-mers)
+// ---------------------------------------------------------------------------
+// A site keeps one bit in each of: occupied by an H k-mer, by a V k-mer, H
+// anchor, V anchor (the parent site of Sec. II.E).  The labelling wave needs,
+// for every contact of a new k-mer, the k-mer on the other side: a k-mer that
+// crosses the new one's side line ends or starts right there (it cannot
+// reach the new k-mer's sites), so its anchor is known outright; one lying
+// along the side line is found from the anchor bits, its first contact at an
+// anchor or at the side's first site (there by the nearest anchor before
+// it); a k-mer met at an end of the new one is either of these.  The
+// canonical placement index of that anchor gives the deposit number through
+// an open-addressing table written as k-mers are labelled.  Occupancies are
+// read along rows (H deposits' sides) and along columns (V deposits'); a
+// copy written across its lines is tiled 16 lines to a 128-byte tile so the
+// k bits a deposit sets there touch k/16 lines.  Bitmap words and table
+// slots are changed by atomics at L2 and read with L2-scope loads.
+
+__device__ __forceinline__ uint32_t word_plain(const Ctx &c, uint32_t line, uint32_t w) { return line * c.nlw + w; }
+__device__ __forceinline__ uint32_t word_tiled(const Ctx &c, uint32_t line, uint32_t w)
+{
+    return ((w * c.nt16 + (line >> 4)) << 4) + (line & 15u);
+}
+
+__device__ __forceinline__ uint64_t ld_l2(const uint64_t *p)
+{
+    return __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void or_l2(uint64_t *p, uint64_t m)
+{
+    if (m) atomicOr((unsigned long long *)p, (unsigned long long)m);
+}
+
+// Bit `pos` along line `line` of a bitmap (plain or tiled).
+__device__ __forceinline__ uint32_t bit_plain(const Ctx &c, const uint64_t *bm, uint32_t line, uint32_t pos)
+{
+    return (uint32_t)(ld_l2(&bm[word_plain(c, line, pos >> 6)]) >> (pos & 63u)) & 1u;
+}
+__device__ __forceinline__ uint32_t bit_tiled(const Ctx &c, const uint64_t *bm, uint32_t line, uint32_t pos)
+{
+    return (uint32_t)(ld_l2(&bm[word_tiled(c, line, pos >> 6)]) >> (pos & 63u)) & 1u;
+}
+
+// Placement -> deposit number: slots of (P + 1) | t << 32, linear probing
+// from a multiplicative hash.
+__device__ __forceinline__ uint32_t kh_slot(const Ctx &c, uint32_t P)
+{
+    return (uint32_t)((P * 0x9E3779B1u) >> (32 - c.hlg));
+}
+
+__device__ __forceinline__ void kh_insert(const Ctx &c, uint32_t P, uint32_t t)
+{
+    const uint32_t mask = (1u << c.hlg) - 1;
+    uint32_t sl = kh_slot(c, P);
+    const unsigned long long v = (unsigned long long)(P + 1) | ((unsigned long long)t << 32);
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        if (atomicCAS(&c.khash[sl], 0ull, v) == 0ull) return;
+        sl = (sl + 1) & mask;
+    }
+}
+
+// Deposit number of the k-mer placed at P, or -1 if the table has none.
+__device__ __forceinline__ int32_t kh_find(const Ctx &c, uint32_t P)
+{
+    const uint32_t mask = (1u << c.hlg) - 1;
+    uint32_t sl = kh_slot(c, P);
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        const unsigned long long e =
+            __hip_atomic_load(&c.khash[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)e == P + 1) return (int32_t)(e >> 32);
+        if (e == 0ull) return -1;
+        sl = (sl + 1) & mask;
+    }
+    return -1;
+}
+
+// Set bits [a, a + len) (cyclic, len <= L) along line `line` of a plain
+// bitmap: the wave's lanes take one word each.
+__device__ __forceinline__ void set_run_plain(const Ctx &c, uint64_t *bm, uint32_t line, uint32_t a, uint32_t len)
+{
+    const uint32_t L = c.L, lane = lane_id();
+    const uint32_t e1 = a + len < L ? a + len : L;   // [a, e1) then [0, a + len - L)
+    const uint32_t n1 = ((e1 - 1) >> 6) - (a >> 6) + 1;
+    const uint32_t e2 = a + len > L ? a + len - L : 0;
+    const uint32_t n2 = e2 ? ((e2 - 1) >> 6) + 1 : 0;
+    for (uint32_t i = lane; i < n1 + n2; i += 64) {
+        uint32_t w, lo, hi;   // word and the run's positions in it, [lo, hi)
+        if (i < n1) {
+            w = (a >> 6) + i;
+            lo = w * 64 > a ? w * 64 : a;
+            hi = w * 64 + 64 < e1 ? w * 64 + 64 : e1;
+        } else {
+            w = i - n1;
+            lo = w * 64;
+            hi = w * 64 + 64 < e2 ? w * 64 + 64 : e2;
+        }
+        or_l2(&bm[word_plain(c, line, w)], bit_range((int32_t)(lo - w * 64), (int32_t)(hi - w * 64) - 1));
+    }
+}
+
+// Nearest set bit at or before position p, cyclically, within distance d
+// (positions p - d .. p) along line `line` of a plain bitmap; ~0u if none.
+// All lanes of the wave take part.
+__device__ __forceinline__ uint32_t nearest_before(const Ctx &c, const uint64_t *bm, uint32_t line, uint32_t p,
+                                                   uint32_t d)
+{
+    const uint32_t L = c.L, lane = lane_id(), nw = c.nlw;
+    const uint32_t pw = p >> 6;
+    // words pw, pw - 1, ... back round the line (one more than full words
+    // would need: crossing the seam passes the line's short last word); the
+    // last step (back at pw) holds the positions after p, reached only when
+    // d spans almost all of L
+    uint32_t steps = (d + 63) / 64 + 2;
+    steps = steps < nw ? steps : nw;
+    const bool wrapback = d + 64 >= L;
+    const uint32_t total = steps + (wrapback ? 1u : 0u);
+    for (uint32_t l0 = 0; l0 < total; l0 += 64) {
+        const uint32_t l = l0 + lane;
+        uint32_t cand = ~0u;
+        if (l < total) {
+            const bool again = wrapback && l == total - 1;   // pw's positions after p
+            uint32_t w = again ? pw : (pw + nw * 2 - (l % nw)) % nw;
+            const uint32_t valid = w == nw - 1 && (L & 63u) ? (L & 63u) : 64u;
+            uint64_t m = ld_l2(&bm[word_plain(c, line, w)]) & (valid == 64 ? ~0ull : ((1ull << valid) - 1));
+            if (!again && l == 0) m &= bit_range(0, (int32_t)(p & 63u));
+            if (again) m &= ~bit_range(0, (int32_t)(p & 63u));
+            if (m) {
+                const uint32_t q = w * 64 + (63 - __clzll((long long)m));
+                const uint32_t dist = p >= q ? p - q : p + L - q;
+                if (dist <= d) cand = q;
+            }
+        }
+        const uint64_t hit = __ballot(cand != ~0u);
+        if (hit) return bcast(cand, first_lane(hit));
+    }
+    return ~0u;
+}
+
+// Write the k-mers of a labelling batch into the bitmaps and the table.
+__device__ __forceinline__ void cl_write_batch(const Ctx &c, uint32_t tl, uint32_t B)
+{
+    const uint32_t L = c.L, k = c.k, lane = lane_id();
+    for (uint32_t i = 0; i < B; ++i) {
+        const uint32_t a = uniform(lds_peek(&c.banc[i]));
+        const uint32_t om = a >> 31, site = a & 0x7FFFFFFFu;
+        const uint32_t ay = fdiv(site, c.fL), ax = site - ay * L;
+        if (om == 0) {
+            set_run_plain(c, c.ohr, ay, ax, k);   // along its row
+            for (uint32_t j = lane; j < k; j += 64) {   // across its columns
+                uint32_t col = ax + j;
+                col = col >= L ? col - L : col;
+                or_l2(&c.ohc[word_tiled(c, col, ay >> 6)], 1ull << (ay & 63u));
+            }
+            if (lane == 0) or_l2(&c.ahr[word_plain(c, ay, ax >> 6)], 1ull << (ax & 63u));
+        } else {
+            set_run_plain(c, c.ovc, ax, ay, k);   // along its column
+            for (uint32_t j = lane; j < k; j += 64) {   // across its rows
+                uint32_t row = ay + j;
+                row = row >= L ? row - L : row;
+                or_l2(&c.ovr[word_tiled(c, row, ax >> 6)], 1ull << (ax & 63u));
+            }
+            if (lane == 0) or_l2(&c.avc[word_plain(c, ax, ay >> 6)], 1ull << (ay & 63u));
+        }
+        if (lane == 0) kh_insert(c, om * L * L + site, tl + i);
+    }
+}
+
+// Contact f of deposit m (anchor ay, ax, orientation om) on the compressed
+// lattice: whether a neighbouring k-mer's contact starts there (the first
+// contact of that k-mer on this side, the side's first contact, or an end),
+// and that k-mer's canonical placement index.  `back` is the anchor found
+// before the side's first site (only read at f == side start with an H
+// (resp. V) k-mer along the side that is not anchored there).
+struct ClContact {
+    bool emit;
+    uint32_t P;
+};
+
+// A placement index no k-mer has (its table key would be 0xFFFFFFFF): a
+// lookup of it fails and the broken invariant is reported.
+constexpr uint32_t kNoPlacement = 0xFFFFFFFEu;
+
+__device__ __forceinline__ ClContact cl_contact(const Ctx &c, uint32_t om, uint32_t ay, uint32_t ax, uint32_t f,
+                                                uint32_t back0, uint32_t back1)
+{
+    const uint32_t L = c.L, k = c.k;
+    ClContact r;
+    r.emit = false;
+    r.P = 0;
+    const uint32_t L2 = L * L;
+    const auto wrap = [&](uint32_t v) { return v >= L ? v - L : v; };
+    if (f < 2 * k) {
+        const uint32_t side = f < k ? 0u : 1u, j = f - side * k;
+        if (om == 0) {   // rows ay -+ 1, columns ax + j
+            const uint32_t row = side ? wrap(ay + 1) : wrap(ay + L - 1), col = wrap(ax + j);
+            if (bit_tiled(c, c.ovr, row, col)) {
+                // a V k-mer crossing the row ends at ay - 1 / starts at ay + 1
+                const uint32_t ar = side ? wrap(ay + 1) : wrap(ay + L - k);
+                r.emit = true;
+                r.P = L2 + ar * L + col;
+            } else if (bit_plain(c, c.ohr, row, col)) {
+                const bool anc = bit_plain(c, c.ahr, row, col) != 0;
+                if (anc || j == 0) {
+                    const uint32_t ac = anc ? col : (side ? back1 : back0);
+                    r.emit = true;
+                    r.P = ac != ~0u ? row * L + ac : kNoPlacement;
+                }
+            }
+        } else {         // columns ax -+ 1, rows ay + j
+            const uint32_t col = side ? wrap(ax + 1) : wrap(ax + L - 1), row = wrap(ay + j);
+            if (bit_tiled(c, c.ohc, col, row)) {
+                // an H k-mer crossing the column ends at ax - 1 / starts at ax + 1
+                const uint32_t ac = side ? wrap(ax + 1) : wrap(ax + L - k);
+                r.emit = true;
+                r.P = row * L + ac;
+            } else if (bit_plain(c, c.ovc, col, row)) {
+                const bool anc = bit_plain(c, c.avc, col, row) != 0;
+                if (anc || j == 0) {
+                    const uint32_t ar = anc ? row : (side ? back1 : back0);
+                    r.emit = true;
+                    r.P = ar != ~0u ? L2 + ar * L + col : kNoPlacement;
+                }
+            }
+        }
+    }
+    return r;
+}
+
+// Census of the jammed state on the compressed lattice (Eq. 12): over every
+// site and its right (lower) neighbour, pairs of occupied sites in different
+// k-mers, both H, both V or perpendicular.  Two H sites side by side along a
+// row are different k-mers exactly when the right one is an anchor (and
+// k < L); two V sites side by side along a row always are.  Likewise down
+// the columns.
+template <uint32_t NT>
+__device__ __forceinline__ void contact_census_bits(const Ctx &c, uint32_t tid)
+{
+    const uint32_t L = c.L, nw = c.nlw;
+    const uint32_t tail = L & 63u;
+    const bool kfull = c.k == L;
+    uint64_t n[3] = {0, 0, 0};
+    // dir 0: rows (H along, V across); dir 1: columns (V along, H across)
+    for (uint32_t dir = 0; dir < 2; ++dir) {
+        const uint64_t *along = dir ? c.ovc : c.ohr;   // same orientation as the line
+        const uint64_t *anc = dir ? c.avc : c.ahr;
+        const uint64_t *cross = dir ? c.ohc : c.ovr;   // the other orientation, tiled
+        for (uint32_t i = tid; i < L * nw; i += NT) {
+            const uint32_t line = i / nw, w = i - line * nw;
+            const uint32_t wn = w + 1 == nw ? 0u : w + 1;   // next word (round the seam)
+            const uint32_t valid = w + 1 == nw && tail ? tail : 64u;
+            const uint64_t vmask = valid == 64 ? ~0ull : ((1ull << valid) - 1);
+            const uint64_t s = ld_l2(&along[word_plain(c, line, w)]);
+            const uint64_t x = ld_l2(&cross[word_tiled(c, line, w)]);
+            const uint64_t a = ld_l2(&anc[word_plain(c, line, w)]);
+            const uint64_t s1 = ld_l2(&along[word_plain(c, line, wn)]) & 1ull;
+            const uint64_t x1 = ld_l2(&cross[word_tiled(c, line, wn)]) & 1ull;
+            const uint64_t a1 = ld_l2(&anc[word_plain(c, line, wn)]) & 1ull;
+            // the neighbour one step along the line, bit for bit
+            const uint64_t sn = (s >> 1) | (s1 << (valid - 1));
+            const uint64_t xn = (x >> 1) | (x1 << (valid - 1));
+            const uint64_t an = (a >> 1) | (a1 << (valid - 1));
+            const uint64_t same_o = kfull ? 0ull : (s & sn & an);   // along-orientation pair, new k-mer
+            const uint64_t cross_o = x & xn;                        // across-orientation pair
+            const uint64_t perp = (s & xn) | (x & sn);
+            // dir 0: along = H -> n_x, across = V -> n_y; dir 1 the opposite
+            n[dir] += (uint64_t)__popcll(same_o & vmask);
+            n[1 - dir] += (uint64_t)__popcll(cross_o & vmask);
+            n[2] += (uint64_t)__popcll(perp & vmask);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const uint64_t w = wave_sum64(n[j]);
+        if ((tid & 63) == 0 && w) atomicAdd(&c.h->ncon[j], (unsigned long long)w);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Labelling wave: site map, contacts, union-find with displacements
 // ---------------------------------------------------------------------------
 
@@ -1847,7 +2130,20 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track, bool fill_map)
 {
     const uint32_t lane = lane_id();
     const uint32_t L = c.L, k = c.k, nC = 2 * k + 2;
-    if (fill_map) {
+    const bool cl = SIDE && c.compressed;
+    if (fill_map && cl) {
+        // the compressed lattice: six bitmaps and the placement table, zero
+        // (each bitmap area is a whole number of 128-byte tiles)
+        const size_t nwb = (size_t)c.nlw * c.nt16 * 16;
+        uint64_t *const bms[6] = {c.ohr, c.ovr, c.ohc, c.ovc, c.ahr, c.avc};
+        for (int b = 0; b < 6; ++b) {
+            ulonglong2 *q = (ulonglong2 *)bms[b];
+            for (size_t i = lane; i < nwb / 2; i += 64) q[i] = make_ulonglong2(0ull, 0ull);
+        }
+        ulonglong2 *hq = (ulonglong2 *)c.khash;
+        for (size_t i = lane; i < ((size_t)1 << c.hlg) / 2; i += 64) hq[i] = make_ulonglong2(0ull, 0ull);
+        __builtin_amdgcn_s_waitcnt(0);   // the zeros are in L2 before any atomic on them
+    } else if (fill_map) {
         // the padded map (a multiple of 32 x 32 sites)
         int4 *m4 = (int4 *)c.map;
         const size_t q4 = (size_t)c.lp() * c.lp() / 4;
@@ -1898,7 +2194,10 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track, bool fill_map)
         if (lane == 0) lds_store(&c.h->lab_progress, t1);
         // site map of the batch; long k-mers (sparse-clear kernels) walk
         // each k-mer along its line, decoding its anchor once
-        if (SIDE && k >= kSideGather) {
+        if (cl) {
+            cl_write_batch(c, tl, B);
+            __builtin_amdgcn_s_waitcnt(0);   // every atomic of the batch done before its reads
+        } else if (SIDE && k >= kSideGather) {
             for (uint32_t i = 0; i < B; ++i) {
                 const uint32_t a = uniform(lds_peek(&c.banc[i]));
                 const uint32_t om = a >> 31, site = a & 0x7FFFFFFFu;
@@ -1911,7 +2210,7 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track, bool fill_map)
                 }
             }
         }
-        for (uint32_t q = lane; !(SIDE && k >= kSideGather) && q < B * k; q += 64) {
+        for (uint32_t q = lane; !cl && !(SIDE && k >= kSideGather) && q < B * k; q += 64) {
             uint32_t i = fdiv(q, c.fk);
             uint32_t s = q - i * k;
             uint32_t a = c.banc[i];
@@ -1952,7 +2251,163 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track, bool fill_map)
         const bool dedupe = k != L;
         bool stop = false;
         const bool side_gather = SIDE && k >= kSideGather;
-        if (side_gather) {
+        if (cl) {
+            // compressed lattice: the sides are read a word (64 sites) per
+            // lane; a neighbour k-mer's contact starts where its anchor or its
+            // crossing is met (or at the side's first site); the candidates
+            // go through the placement table together
+            for (uint32_t i = 0; i < B && !stop; ++i) {
+                const uint32_t m = tl + i;
+                const uint32_t a = uniform(lds_peek(&c.banc[i]));
+                const uint32_t om = a >> 31, site = a & 0x7FFFFFFFu;
+                const uint32_t ay = fdiv(site, c.fL), ax = site - ay * L;
+                const auto wrap = [&](uint32_t v) { return v >= L ? v - L : v; };
+                // sides: H deposit rows ay -+ 1 along columns from ax (H occupancy
+                // along, V across); V deposit columns ax -+ 1 along rows from ay
+                const uint64_t *const along = om ? c.ovc : c.ohr;
+                const uint64_t *const cross = om ? c.ohc : c.ovr;
+                const uint64_t *const anc = om ? c.avc : c.ahr;
+                const uint32_t pst = om ? ay : ax;
+                const uint32_t line0 = om ? wrap(ax + L - 1) : wrap(ay + L - 1);
+                const uint32_t line1 = om ? wrap(ax + 1) : wrap(ay + 1);
+                const Span sp = make_span(c, pst, k);
+                // ---- reads: the first site of each side, the end sites, the words
+                const uint32_t f0a = bit_plain(c, along, line0, pst), f0n = bit_plain(c, anc, line0, pst);
+                const uint32_t f1a = bit_plain(c, along, line1, pst), f1n = bit_plain(c, anc, line1, pst);
+                // ends (before site 0, after site k-1): occupied along the deposit's
+                // own line (same orientation) or across it
+                const uint32_t e0 = om ? wrap(ay + L - 1) : wrap(ax + L - 1);
+                const uint32_t e1 = om ? wrap(ay + k) : wrap(ax + k);
+                const uint32_t own = om ? ax : ay;   // the deposit's own line
+                const uint32_t e0s = bit_plain(c, along, own, e0), e1s = bit_plain(c, along, own, e1);
+                const uint32_t e0x = bit_tiled(c, cross, own, e0), e1x = bit_tiled(c, cross, own, e1);
+                // ---- anchors found by search (only where needed)
+                const uint32_t back0 = (f0a && !f0n) ? nearest_before(c, anc, line0, pst, k - 1) : ~0u;
+                const uint32_t back1 = (f1a && !f1n) ? nearest_before(c, anc, line1, pst, k - 1) : ~0u;
+                // a k-mer across the deposit's line at an end: its anchor is the
+                // nearest one before along the end's line (the other bitmap)
+                const uint64_t *const anc_x = om ? c.ahr : c.avc;
+                const uint32_t x0 = (!e0s && e0x) ? nearest_before(c, anc_x, e0, own, k - 1) : ~0u;
+                const uint32_t x1 = (!e1s && e1x) ? nearest_before(c, anc_x, e1, own, k - 1) : ~0u;
+                // ---- candidates, 64 per round: lane l takes word item l of the
+                // two sides' windows (first round), then the ends
+                const uint32_t nitems = 2 * sp.n;
+                for (uint32_t r0 = 0; r0 < nitems + 2 && !stop; r0 += 64) {
+                    const uint32_t it = r0 + lane;
+                    uint64_t emitA = 0, emitX = 0;   // along / across contacts in this lane's word
+                    uint32_t sd = 0, w = 0;
+                    if (it < nitems) {
+                        sd = it >= sp.n ? 1u : 0u;
+                        w = span_block(sp, it - sd * sp.n);
+                        const uint32_t ln = sd ? line1 : line0;
+                        const uint64_t wa = ld_l2(&along[word_plain(c, ln, w)]);
+                        const uint64_t wx = ld_l2(&cross[word_tiled(c, ln, w)]);
+                        const uint64_t wn = ld_l2(&anc[word_plain(c, ln, w)]);
+                        // window positions in this word: [pst, pst + k) cyclic
+                        const uint32_t b0 = w * 64;
+                        uint64_t win = 0;
+                        {
+                            const uint32_t e1p = pst + k < L ? pst + k : L;   // [pst, e1p)
+                            const int32_t lo = (int32_t)(pst > b0 ? pst : b0), hi = (int32_t)(e1p < b0 + 64 ? e1p : b0 + 64);
+                            if (lo < hi) win |= bit_range(lo - (int32_t)b0, hi - 1 - (int32_t)b0);
+                            if (pst + k > L) {   // [0, pst + k - L)
+                                const uint32_t e2p = pst + k - L;
+                                const int32_t hi2 = (int32_t)(e2p < b0 + 64 ? e2p : b0 + 64);
+                                if ((int32_t)b0 < hi2) win |= bit_range(0, hi2 - 1 - (int32_t)b0);
+                            }
+                        }
+                        const uint64_t first = (pst >> 6) == w ? (1ull << (pst & 63u)) : 0ull;
+                        emitX = wx & win;
+                        emitA = wa & win & (wn | first);
+                    } else if (it < nitems + 2) {
+                        // ends: one contact each, carried in bit 0
+                        const uint32_t e = it - nitems;
+                        const uint32_t es = e ? e1s : e0s, ex = e ? e1x : e0x;
+                        emitA = es ? 1ull : 0ull;
+                        emitX = (!es && ex) ? 1ull : 0ull;
+                        sd = 2 + e;
+                    }
+                    // one candidate per lane per pass until every lane is done
+                    for (;;) {
+                        const bool have = (emitA | emitX) != 0;
+                        if (__ballot(have) == 0) break;
+                        uint32_t f = 0, P = kNoPlacement;
+                        if (have) {
+                            const bool isA = emitA != 0;
+                            const uint64_t bits = isA ? emitA : emitX;
+                            const uint32_t b = (uint32_t)(__ffsll((long long)bits) - 1);
+                            if (isA) emitA &= emitA - 1; else emitX &= emitX - 1;
+                            if (sd < 2) {
+                                const uint32_t pos = w * 64 + b;               // along the side line
+                                uint32_t j = pos + L - pst;
+                                j = j >= L ? j - L : j;
+                                f = sd * k + j;
+                                const uint32_t ln = sd ? line1 : line0;
+                                if (isA) {
+                                    // a k-mer along the side: anchored here, or (first site)
+                                    // at the anchor found before it
+                                    const uint32_t an = (pos == pst && !(sd ? f1n : f0n)) ? (sd ? back1 : back0) : pos;
+                                    if (an != ~0u) P = om ? (L * L + an * L + ln) : (ln * L + an);
+                                } else {
+                                    // a k-mer across the side ends (side 0) or starts (side 1)
+                                    // next to the deposit's line
+                                    const uint32_t at = sd ? (own + 1 == L ? 0u : own + 1) : wrap(own + L - k);
+                                    P = om ? (pos * L + at) : (L * L + at * L + pos);
+                                }
+                            } else {
+                                const uint32_t e = sd - 2;
+                                f = 2 * k + e;
+                                const uint32_t ep = e ? e1 : e0;   // position of the end on the own line
+                                if (isA) {
+                                    // a k-mer along the deposit's line ends at / starts after it
+                                    const uint32_t at = e ? ep : wrap(pst + L - (k % L));
+                                    P = om ? (L * L + at * L + own) : (own * L + at);
+                                } else {
+                                    const uint32_t an = e ? x1 : x0;   // anchor on the end's line
+                                    if (an != ~0u) P = om ? (ep * L + an) : (L * L + an * L + ep);
+                                }
+                            }
+                        }
+                        int32_t n = -1;
+                        if (have) n = kh_find(c, P);
+                        if (have && n < 0) c.h->status = kErrLabel;   // an occupied site with no k-mer
+                        const bool keep = n >= 0 && (uint32_t)n <= m;
+                        const uint64_t bal = __ballot(keep);
+                        if (keep) {
+                            const uint32_t idx = ne + lanes_below(bal);
+                            c.e_step[idx] = m;
+                            c.e_ms()[idx] = (uint32_t)n;
+                            c.e_vx()[idx] = (int32_t)f;
+                        }
+                        ne += (uint32_t)__popcll(bal);
+                        __builtin_amdgcn_wave_barrier();
+                        if (ne + 64 > kEdges) {
+                            if (prof) {
+                                p_gather += tick() - p0;
+                                p_edges += ne;
+                            }
+                            process_chunk(c, ls, ne);
+                            if (prof) p0 = tick();
+                            ne = 0;
+                            if (!track && ls.nx >= 0 && ls.ny >= 0) stop = true;
+                            if (c.h->status != 0) stop = true;
+                            if (stop) break;
+                        }
+                    }
+                }
+                if (i + 1 == B && !stop) {
+                    if (prof) {
+                        p_gather += tick() - p0;
+                        p_edges += ne;
+                    }
+                    process_chunk(c, ls, ne);
+                    if (prof) p0 = tick();
+                    ne = 0;
+                    if (!track && ls.nx >= 0 && ls.ny >= 0) stop = true;
+                    if (c.h->status != 0) stop = true;
+                }
+            }
+        } else if (side_gather) {
             // Long k-mers: deposit by deposit, side by side.  A side's
             // contacts lie on one lattice line (the row above / below an H
             // k-mer, the column left / right of a V one), so lane j's site
@@ -2023,7 +2478,7 @@ __device__ __forceinline__ void labeler(Ctx &c, bool track, bool fill_map)
                 }
             }
         }
-        for (uint32_t g0 = 0; !side_gather && g0 < total && !stop; g0 += 64 * G) {
+        for (uint32_t g0 = 0; !cl && !side_gather && g0 < total && !stop; g0 += 64 * G) {
             int32_t nval[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -2216,7 +2671,7 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
     c.lg_tr = d.lg_tr;
     c.lg_mr = d.lg_mr;
     c.spec_rows = d.spec_rows;
-    SlabLayout s = slab_layout(d.L, d.k);
+    SlabLayout s = slab_layout(d.L, d.k, d.compressed != 0);
     c.av0 = (uint64_t *)(slab + s.avail0);
     c.av1 = (uint64_t *)(slab + s.avail1);
     c.sm0 = (uint64_t *)(slab + s.sum0);
@@ -2240,6 +2695,17 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
     c.dD = (uint32_t *)(lds + l.total);
     c.dC = c.dD + interval_diff_words(d.k);
     c.fB = d.fB;
+    c.compressed = d.compressed;
+    c.nlw = line_words(d.L);
+    c.nt16 = tile16(d.L);
+    c.hlg = 31 - __clz(hash_slots(d.L, d.k));
+    c.ohr = (uint64_t *)(slab + s.ohr);
+    c.ovr = (uint64_t *)(slab + s.ovr);
+    c.ohc = (uint64_t *)(slab + s.ohc);
+    c.ovc = (uint64_t *)(slab + s.ovc);
+    c.ahr = (uint64_t *)(slab + s.ahr);
+    c.avc = (uint64_t *)(slab + s.avc);
+    c.khash = (unsigned long long *)(slab + s.khash);
 }
 
 // One sample on one workgroup.  deadline = 0 runs it from the empty lattice
@@ -2278,7 +2744,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
         }
         stop = (uint32_t)nany;
     }
-    SampleState *st = (SampleState *)(slab + slab_layout(d.L, d.k).state);
+    SampleState *st = (SampleState *)(slab + slab_layout(d.L, d.k, d.compressed != 0).state);
     uint32_t *saved_cnt = (uint32_t *)((uint8_t *)st + kStateBytes);
     const uint32_t phase = sliced ? st->phase : 0u;
     if (phase == 2) {
@@ -2476,7 +2942,10 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
     // ---- contact census at jamming (Eq. 12)
     if constexpr (CENSUS) {
         if (contacts && c.h->status == 0) {
-            contact_census<NT>(c, tid);
+            if (SPARSE && c.compressed)
+                contact_census_bits<NT>(c, tid);
+            else
+                contact_census<NT>(c, tid);
             __syncthreads();
         }
     }
@@ -2565,7 +3034,7 @@ __global__ void rsa_prepare_launch(const DevDesc *descs, uint32_t n, DevResult *
     res[i].status = kStatusNotRun;
     const DevDesc d = descs[i];
     if (d.flags & kDescFresh) {
-        SampleState *st = (SampleState *)((uint8_t *)d.slab + slab_layout(d.L, d.k).state);
+        SampleState *st = (SampleState *)((uint8_t *)d.slab + slab_layout(d.L, d.k, d.compressed != 0).state);
         st->phase = 0;
     }
 }

@@ -140,6 +140,11 @@ int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, int census, uint
 // counts fit the workgroup's LDS beside the row counts.  Otherwise the sparse
 // clear by summary bits.
 bool use_interval(uint32_t L, uint32_t k, int tile, size_t lds_max);
+// Whether a sample keeps the compressed lattice (occupancy and anchor bitmaps
+// instead of the int32 site map): sparse-clear tiles with k >= kCompressMinK.
+bool use_compressed(uint32_t L, uint32_t k, int tile);
+// Slab bytes of a sample under its tile.
+size_t sample_slab(uint32_t L, uint32_t k, int tile);
 // Dynamic LDS bytes the sample's kernel needs.
 uint32_t sample_lds(uint32_t L, uint32_t k, int tile, size_t lds_max);
 // Kernel-side descriptor of a sample; `out` is its index in the result array.

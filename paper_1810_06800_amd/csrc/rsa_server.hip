@@ -395,7 +395,7 @@ int rsa_server_submit(rsa_server *v, const rsa_sample_t *s, uint32_t n, uint64_t
         if (s[i].flags & RSA_FLAG_CLUSTER_SIZES)
             return fail(c, RSA_EINVAL, "cluster sizes are a batch feature (rsa_batch_cluster_sizes)");
         if (lds_layout(s[i].L).total + 64 > c->lds_max) return fail(c, RSA_EINVAL, "lattice too large for LDS");
-        if (Arena::round(slab_layout(s[i].L, s[i].k).total) > v->arena.size())
+        if (Arena::round(sample_slab(s[i].L, s[i].k, sample_tile(c, s[i].L, s[i].k))) > v->arena.size())
             return fail(c, RSA_ENOMEM, "sample larger than the server arena");
     }
     const uint64_t id = v->next_req++;
@@ -410,7 +410,7 @@ int rsa_server_submit(rsa_server *v, const rsa_sample_t *s, uint32_t n, uint64_t
         sm.s = s[i];
         sm.tile = sample_tile(c, s[i].L, s[i].k);
         sm.key = group_key(s[i], sm.tile);
-        sm.bytes = slab_layout(s[i].L, s[i].k).total;
+        sm.bytes = sample_slab(s[i].L, s[i].k, sm.tile);
         v->queue.push_back(h);
     }
     ++v->st.requests_submitted;

@@ -62,14 +62,26 @@ def test_footprint_matches_layout(rsa):
         counts = r16((rows + 1) // 2 * 4) + r16((rows + 63) // 64 * 4) + r16((rows + 4095) // 4096 * 4)
         nb = (L + k) // (k + 1)
         buckets = 2 * a(4 * nb * lp) if nb <= 64 else 0
-        return (a(lp * wp * 8) * 2 + summary * 2 + a(4 * lp * lp) + a(16 * cap) + a(4 * cap)
-                + a(256 + counts) + buckets)
+        # long k-mers (k >= 512, the sparse-clear tiles the heuristic picks)
+        # keep six one-bit-per-site bitmaps and a placement table of a power
+        # of two >= 2 (L^2/k + 1) 8-byte slots instead of the int32 map
+        compressed = k >= 512
+        site_map = 0 if compressed else a(4 * lp * lp)
+        slots = 64
+        while slots < 2 * (L * L // k + 1):
+            slots *= 2
+        bitmaps = 6 * a(((L + 63) // 64) * ((L + 15) // 16) * 16 * 8) + a(8 * slots) if compressed else 0
+        return (a(lp * wp * 8) * 2 + summary * 2 + site_map + a(16 * cap) + a(4 * cap)
+                + a(256 + counts) + buckets + bitmaps)
 
     for L, k in [(1, 1), (5, 3), (64, 8), (1024, 64), (16384, 1024), (32768, 4096), (16384, 2),
-                 (130, 1), (4096, 63)]:
+                 (130, 1), (4096, 63), (4097, 4097), (600, 512), (1000, 511)]:
         assert rsa.footprint_bytes(L, k) == expect(L, k)
     assert rsa.footprint_bytes(1024, 64) < 5 * 2**20
-    assert 4.2 * 2**30 < rsa.footprint_bytes(32768, 4096) < 4.4 * 2**30
+    # the compressed lattice: one byte per site at L = 32768, k = 4096 (two
+    # availability and six lattice bits), down from 4.3 GiB with the int32 map
+    assert 1.0 * 2**30 < rsa.footprint_bytes(32768, 4096) < 1.1 * 2**30
+    assert rsa.footprint_bytes(16384, 1024) < 0.3 * 2**30
     for L, k in [(0, 0), (4, 5), (32769, 8), (8, 0)]:
         assert rsa.footprint_bytes(L, k) == 0
 

@@ -357,6 +357,42 @@ def test_full_ring_kmers_at_the_row_width_limit(ctx, orc):
         assert max(g["n_wrap_x"], g["n_wrap_y"]) == d[0]
 
 
+def test_long_kmers_interval_clear_and_compressed_lattice(ctx, orc):
+    """Long k-mers (k >= 512): the interval clear (anchor-interval buckets) and
+    the compressed lattice (occupancy and anchor bitmaps with the placement
+    table instead of the site map), on narrow and wide rows, ragged L % 64,
+    k = L, k near L/2, with every statistic flag, under every selecting-wave
+    count; and the summary-bit clear where the interval one does not apply
+    (k > 4096)."""
+    from paper_1810_06800_amd import rsa
+
+    descs = [(512, 512, 3, 0, 0), (600, 512, 3, 1, 2), (1000, 513, 4, 0, 4), (1024, 600, 4, 1, 0),
+             (1500, 700, 5, 0, 6), (2048, 512, 5, 1, 0), (2999, 1499, 6, 0, 2), (4100, 1025, 6, 1, 4),
+             (4097, 2100, 7, 0, 0), (5000, 2600, 7, 1, 2), (8192, 4097, 8, 0, 6)]
+    descs += [(1100, 550, 9, s, 0) for s in range(6)]
+    want = orc.run_many(descs, threads=min(16, os.cpu_count() or 1))
+    _log(f"long k-mers: {len(descs)} samples, default tiles")
+    got = ctx.run(descs)
+    check(descs, got, want, census=True)
+    for d, g, w in zip(descs, got, want):
+        if d[4] & 4:
+            assert (g["n_contacts_x"], g["n_contacts_y"], g["n_contacts_xy"]) == \
+                orc.contacts_at_jamming(*d[:4]), d
+    try:
+        for waves in range(5):
+            tile = rsa.tile_for_shape(1024, 600)
+            w0, tr, mr, sp = rsa.tile_shape(tile)
+            # same bitmap / map tiles and clear mode, each wave count
+            t = next(t for t in range(rsa.num_tiles())
+                     if rsa.tile_shape(t) == ((1, 2, 3, 7, 15)[waves], tr, mr, sp))
+            ctx.set_option(rsa.OPT_TILE, t)
+            sub = descs[:8]
+            _log(f"long k-mers: tile {t} ({rsa.tile_shape(t)})")
+            check(sub, ctx.run(sub), want[:8], census=True)
+    finally:
+        ctx.set_option(rsa.OPT_TILE, -1)
+
+
 def test_small_budget_reuses_slabs(orc):
     """A context whose memory budget holds only a few slabs runs a larger
     batch with a few workgroups, each taking sample after sample on the same

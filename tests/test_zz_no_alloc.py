@@ -39,8 +39,10 @@ def test_static_entry_point_matches_run_batch():
                 assert g["status"] == 0, (d, g["status"])
                 assert g == w, (d, g, w)
         # refusals: nothing is enqueued and the next call still works
+        # (L = 8192, k = 64 keeps a 256 MiB site map: more than the array)
+        assert rsa.footprint_bytes(8192, 64) > rsa.STATIC_SCRATCH_BYTES
         with pytest.raises(rsa.RsaError) as e:
-            ctx.run_batch_static([(8192, 512, 1, 0, 0)])
+            ctx.run_batch_static([(8192, 64, 1, 0, 0)])
         assert e.value.code == rsa.RSA_ENOMEM
         with pytest.raises(rsa.RsaError) as e:
             ctx.run_batch_static([(64, 8, 1, 0, rsa.FLAG_CLUSTER_SIZES)])
