@@ -215,9 +215,11 @@ int rsa_batch_elapsed_ms(rsa_ctx *ctx, uint64_t batch_id, float *ms);
  * (counts), then the select wave's read-ahead outside the clear (planning
  * and issuing the window's reads; 0 with the dense clear, which does both
  * inside) and its clear proper (reads, the deposit's hashes while they are
- * in flight, bits cleared, counts updated) (ticks).  Blocks until the kernels are done; valid until
- * rsa_results.  RSA_EINVAL if the batch was not profiled or n differs from
- * its size. */
+ * in flight, bits cleared, counts updated) (ticks), then, for the interval
+ * clear of long k-mers, the select wave's line cuts, its wait for the other
+ * selecting waves between the clear's two phases, and its row-count phase
+ * (ticks).  Blocks until the kernels are done; valid until rsa_results.
+ * RSA_EINVAL if the batch was not profiled or n differs from its size. */
 int rsa_batch_profile(rsa_ctx *ctx, uint64_t batch_id, uint64_t *out, uint32_t n,
                       uint32_t *slots, uint32_t *clock_khz);
 

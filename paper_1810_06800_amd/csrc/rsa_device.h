@@ -280,6 +280,9 @@ enum ProfSlot {
     kProfSpecHits,      // count: next row read ahead of the clear was the right one
     kProfSelHook,       // read-ahead outside the clear (sparse clear; 0 with the dense one)
     kProfSelProcess,    // the selecting wave's clear: reads, hashes, bits, counts
+    kProfIvCut,         // interval clear, selecting wave: lines cut (reads, writes, counts)
+    kProfIvMeet,        // interval clear, selecting wave: waiting at the mid-step barrier
+    kProfIvRows,        // interval clear, selecting wave: row counts from the cuts
     kProfSlots
 };
 

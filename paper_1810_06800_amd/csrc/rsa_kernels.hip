@@ -51,6 +51,15 @@ constexpr uint32_t kSideGather = 512;   // k from which contacts are gathered si
 template <class T>
 using gmem = __attribute__((address_space(1))) T;
 
+__device__ __forceinline__ uint32_t gld32(const uint32_t *p) { return *(const gmem<uint32_t> *)p; }
+__device__ __forceinline__ void gst32(uint32_t *p, uint32_t v) { *(gmem<uint32_t> *)p = v; }
+__device__ __forceinline__ void gst64(uint64_t *p, uint64_t v) { *(gmem<uint64_t> *)p = v; }
+__device__ __forceinline__ void gand64(uint64_t *p, uint64_t m)
+{
+    __hip_atomic_fetch_and((gmem<unsigned long long> *)p, (unsigned long long)m, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // Small device helpers
 // ---------------------------------------------------------------------------
@@ -196,13 +205,14 @@ struct Hdr {
     uint32_t lab_stop;       // labelling ended early (both wrap steps known)
     uint32_t stop;           // selection ends before this step (0 = at jamming)
     unsigned long long ncon[3];   // contact census: both H, both V, perpendicular
-    unsigned long long sel_acc[7];   // selecting wave's phase counters (profiling)
+    unsigned long long sel_acc[10];  // selecting wave's phase counters (profiling)
     uint32_t bar;            // interval clear: arrivals of the selecting waves at the mid-step barrier
     uint32_t jrs, jn;        // interval clear: V anchors a vertical deposit removed from its own column
 };
 
 // Selecting-wave profile accumulators, kept in LDS rather than in registers.
-enum SelAcc { kAccStart = 0, kAccRing, kAccSelect, kAccClear, kAccHook, kAccProcess, kAccSpec };
+enum SelAcc { kAccStart = 0, kAccRing, kAccSelect, kAccClear, kAccHook, kAccProcess, kAccSpec, kAccIvCut, kAccIvMeet,
+              kAccIvRows };
 
 struct Ctx {
     unsigned long long *prof;   // this sample's counters, or null
@@ -672,57 +682,76 @@ struct LineCut {
 __device__ __forceinline__ uint32_t seg_start(uint32_t v) { return v & 0xFFFFu; }
 __device__ __forceinline__ uint32_t seg_end(uint32_t v) { return v >> 16; }
 
-// Remove the available anchors inside the cyclic range [lo, lo + len)
-// (len >= L: the whole line) from line q of `list`.  Lanes with `act` cut
-// their own line; every touched bucket keeps what lies outside the range.
-__device__ __forceinline__ LineCut cut_line(const Ctx &c, uint32_t *list, uint32_t q, uint32_t lo, uint32_t len,
-                                            bool act)
+// The buckets a cut of the cyclic range [lo, lo + len) (len >= L: the whole
+// line) touches, in increasing order: buckets 0 .. n0 - 1 (the part past the
+// seam), then ja, ja + 1, ...; nj in all, at most four, as the range is
+// shorter than two buckets and the seam splits it at most once.  The same for
+// every line cut with that range.  (Plain fields only: an array indexed at
+// run time would live in scratch memory.)
+struct CutPlan {
+    uint32_t lo, len, wend;
+    uint32_t n0, ja, nj;
+    bool full, wraps, over;
+};
+
+__device__ __forceinline__ uint32_t plan_bucket(const CutPlan &p, uint32_t i)
 {
-    const uint32_t L = c.L, lp = c.lp();
+    return i < p.n0 ? i : p.ja + (i - p.n0);
+}
+
+__device__ __forceinline__ CutPlan cut_plan(const Ctx &c, uint32_t lo, uint32_t len)
+{
+    const uint32_t L = c.L;
+    CutPlan p;
+    p.lo = lo;
+    p.len = len;
+    p.full = len >= L;
+    p.wraps = !p.full && lo + len > L;
+    p.wend = p.wraps ? lo + len - L : 0;   // the range's part past the seam: [0, wend)
+    uint32_t jb;
+    p.n0 = 0;
+    if (p.full) {
+        p.ja = 0;
+        jb = fdiv(L - 1, c.fB);
+    } else if (p.wraps) {
+        const uint32_t jw = fdiv(p.wend - 1, c.fB);
+        p.n0 = jw + 1;
+        const uint32_t j0 = fdiv(lo, c.fB);
+        p.ja = j0 > jw + 1 ? j0 : jw + 1;
+        jb = fdiv(L - 1, c.fB);
+    } else {
+        p.ja = fdiv(lo, c.fB);
+        jb = fdiv(lo + len - 1, c.fB);
+    }
+    const uint32_t n1 = jb >= p.ja ? jb - p.ja + 1 : 0;
+    p.nj = p.n0 + n1;
+    p.over = p.nj > 4;
+    if (p.over) p.nj = 4;
+    return p;
+}
+
+// Read the touched bucket entries of line q (kNoSeg where nothing is read).
+__device__ __forceinline__ void cut_load(const Ctx &c, const CutPlan &p, const uint32_t *list, uint32_t q, bool act,
+                                         uint32_t ev[4])
+{
+    const uint32_t lp = c.lp();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        ev[i] = (act && (uint32_t)i < p.nj) ? gld32(&list[plan_bucket(p, (uint32_t)i) * lp + q]) : kNoSeg;
+}
+
+// Remove the available anchors inside the plan's range from line q, whose
+// touched entries are ev: every touched bucket keeps what lies outside the
+// range, and the entries that change are written back.
+__device__ __forceinline__ LineCut cut_apply(const Ctx &c, const CutPlan &p, uint32_t *list, uint32_t q, bool act,
+                                             const uint32_t ev[4])
+{
+    const uint32_t lp = c.lp(), lo = p.lo, len = p.len, wend = p.wend;
     LineCut r;
     r.n = 0;
     r.nw = 0;
     r.start = 0;
-    r.bad = false;
-    const bool full = len >= L;
-    const bool wraps = !full && lo + len > L;
-    const uint32_t wend = wraps ? lo + len - L : 0;   // the range's part past the seam: [0, wend)
-    // touched buckets, increasing (at most four: a range shorter than two
-    // buckets, split at most once by the seam)
-    uint32_t jv[4];
-    uint32_t nj = 0;
-    uint32_t ja, jb;
-    bool over = false;
-    if (full) {
-        ja = 0;
-        jb = fdiv(L - 1, c.fB);
-    } else if (wraps) {
-        const uint32_t jw = fdiv(wend - 1, c.fB);
-        for (uint32_t j = 0; j <= jw; ++j) {
-            if (nj == 4) {
-                over = true;
-                break;
-            }
-            jv[nj++] = j;
-        }
-        const uint32_t j0 = fdiv(lo, c.fB);
-        ja = j0 > jw + 1 ? j0 : jw + 1;
-        jb = fdiv(L - 1, c.fB);
-    } else {
-        ja = fdiv(lo, c.fB);
-        jb = fdiv(lo + len - 1, c.fB);
-    }
-    for (uint32_t j = ja; j <= jb; ++j) {
-        if (nj == 4) {
-            over = true;
-            break;
-        }
-        jv[nj++] = j;
-    }
-    r.bad = act && over;
-    uint32_t ev[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) ev[i] = (act && (uint32_t)i < nj) ? list[jv[i] * lp + q] : kNoSeg;
+    r.bad = act && p.over;
     int32_t lastw = -1;
     uint32_t prev_e = 0;
     bool first = true;
@@ -733,15 +762,15 @@ __device__ __forceinline__ LineCut cut_line(const Ctx &c, uint32_t *list, uint32
         const int32_t s = (int32_t)seg_start(E), e = (int32_t)seg_end(E);
         // the part of the piece outside the range stays (one interval at most)
         int32_t ks = 1, ke = 0;
-        if (!full) {
-            if (wraps) {   // outside: [wend, lo)
+        if (!p.full) {
+            if (p.wraps) {   // outside: [wend, lo)
                 const int32_t a = s > (int32_t)wend ? s : (int32_t)wend;
                 const int32_t b = e < (int32_t)lo - 1 ? e : (int32_t)lo - 1;
                 if (a <= b) {
                     ks = a;
                     ke = b;
                 }
-            } else {       // outside: [lo + len, L) and [0, lo)
+            } else {         // outside: [lo + len, L) and [0, lo)
                 const int32_t ca = (int32_t)(lo + len);
                 const int32_t a1 = s > ca ? s : ca;
                 const int32_t b2 = e < (int32_t)lo - 1 ? e : (int32_t)lo - 1;
@@ -761,13 +790,13 @@ __device__ __forceinline__ LineCut cut_line(const Ctx &c, uint32_t *list, uint32
         // removed pieces, in increasing position
         int32_t ps0 = s, pe0 = e, ps1 = 0, pe1 = -1;
         if (keep) {
-            pe0 = ks - 1;          // left of what stays (empty if ks == s)
-            ps1 = ke + 1;          // right of it (empty if ke == e)
+            pe0 = ks - 1;   // left of what stays (empty if ks == s)
+            ps1 = ke + 1;   // right of it (empty if ke == e)
             pe1 = e;
         }
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int32_t a = p ? ps1 : ps0, b = p ? pe1 : pe0;
+        for (int h = 0; h < 2; ++h) {
+            const int32_t a = h ? ps1 : ps0, b = h ? pe1 : pe0;
             if (a > b) continue;
             r.n += (uint32_t)(b - a + 1);
             int32_t w0 = a >> 6;
@@ -782,7 +811,7 @@ __device__ __forceinline__ LineCut cut_line(const Ctx &c, uint32_t *list, uint32
             prev_e = (uint32_t)b;
         }
         const uint32_t nv = keep ? ((uint32_t)ks | ((uint32_t)ke << 16)) : kNoSeg;
-        if (nv != E) list[jv[i] * lp + q] = nv;
+        if (nv != E) gst32(&list[plan_bucket(p, (uint32_t)i) * lp + q], nv);
     }
     return r;
 }
@@ -906,9 +935,11 @@ __device__ __forceinline__ bool in_span(const Ctx &c, const Span &sp, uint32_t q
 // the lines (the selecting wave also the deposit's own line), phase two
 // turns the block's cuts into row counts; the selecting waves meet between.
 template <int NSEL>
-__device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_t y, uint32_t x, uint32_t wv,
-                                               uint32_t &wchg, uint32_t &passed)
+__device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_t y, uint32_t x, uint32_t t,
+                                               uint32_t wv, uint32_t &wchg, uint64_t &occ, uint32_t &passed,
+                                               unsigned long long *acc = nullptr)
 {
+    uint64_t pt = acc ? tick() : 0;
     const uint32_t L = c.L, k = c.k, lane = lane_id();
     const uint32_t strip = 2 * k - 1 < L ? 2 * k - 1 : L;
     uint32_t xb = x + L - (k - 1);
@@ -916,99 +947,153 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
     uint32_t yb = y + L - (k - 1);
     yb = yb >= L ? yb - L : yb;
     bool bad = false;
-    // ---- phase one
-    if (wv == 0) {
-        // the deposit's own line: H row y loses [x-k+1, x+k-1], V column x
-        // loses [y-k+1, y+k-1]
-        const LineCut cut = cut_line(c, o ? c.vb : c.hb, o ? x : y, o ? yb : xb, strip, lane == 0);
-        bad = bad || cut.bad;
-        if (lane == 0) {
-            if (o == 0) {
-                if (cut.n) count_sub(c, y, cut.n);
-                wchg += cut.nw;
-            } else {
-                c.h->jrs = cut.start;
-                c.h->jn = cut.n;
-                wchg += cut.n;   // one V word per row of the column
-            }
-        }
-    }
+    // ---- phase one: every read of this wave's share is issued first, so the
+    // share costs one round trip; the occupancy hash of the deposit's sites
+    // (split over the waves) runs while the reads are in flight
+    // the deposit's own line (selecting wave, one lane): H row y loses
+    // [x-k+1, x+k-1], V column x loses [y-k+1, y+k-1]
+    uint32_t *const slist = o ? c.vb : c.hb;
+    const uint32_t sq = o ? x : y;
+    const CutPlan spl = cut_plan(c, o ? yb : xb, strip);
+    const bool sact = wv == 0 && lane == 0;
+    uint32_t sev[4];
+    cut_load(c, spl, slist, sq, sact, sev);
     // the crossing lines: for H, V columns x .. x+k-1 lose rows [y-k+1, y];
-    // for V, H rows y .. y+k-1 lose columns [x-k+1, x]
+    // for V, H rows y .. y+k-1 lose columns [x-k+1, x]; 64-line blocks
+    // round-robin over the waves, up to IV_PF of them read at once
+    constexpr int IV_PF = 4;
     const Span sp = make_span(c, o ? y : x, k);
     uint32_t *const blist = o ? c.hb : c.vb;
     const uint32_t blo = o ? xb : yb;
-    for (uint32_t m = wv; m < sp.n; m += NSEL) {
-        const uint32_t blk = span_block(sp, m);
-        const uint32_t q = blk * 64 + lane;
-        const bool act = in_span(c, sp, q);
-        const LineCut cut = cut_line(c, blist, q, blo, k, act);
-        bad = bad || cut.bad;
-        if (o == 1) {
-            // H row q: its count drops by the anchors removed
-            count_sub_wave(c, act, q, cut.n);
-            wchg += cut.nw;
-            continue;
+    const CutPlan bp = cut_plan(c, blo, k);
+    // (every wave passes once, for its share of the hash, if it has no block)
+    for (uint32_t m0 = wv; m0 == wv || m0 < sp.n; m0 += NSEL * IV_PF) {
+        uint32_t ev[IV_PF][4];
+        uint32_t qv[IV_PF];
+        bool av[IV_PF];
+#pragma unroll
+        for (int f = 0; f < IV_PF; ++f) {
+            const uint32_t m = m0 + (uint32_t)f * NSEL;
+            const uint32_t q = m < sp.n ? span_block(sp, m) * 64 + lane : 0xFFFFFFFFu;
+            av[f] = m < sp.n && in_span(c, sp, q);
+            qv[f] = q;
+            cut_load(c, bp, blist, q, av[f], ev[f]);
         }
-        // V column q: rows blo + [l, h] (block-relative, h < k) lose an anchor
-        const bool has = act && cut.n != 0;
-        uint32_t l = 0;
-        if (has && cut.n < k) {
-            l = cut.start + L - blo;
-            l = l >= L ? l - L : l;
-        }
-        const uint32_t h = l + cut.n - 1;
-        // a cut lies inside the block's k rows; anything else is a broken
-        // invariant and is reported, never written
-        const bool in_block = h < k;
-        bad = bad || (has && !in_block);
-        const bool has_ok = has && in_block;
-        if (has_ok) {
-            atomicAdd(&c.dD[l], 1u);
-            atomicAdd(&c.dC[l >> 6], 1u);
-            if (h + 1 < k) {
-                atomicSub(&c.dD[h + 1], 1u);
-                atomicSub(&c.dC[(h + 1) >> 6], 1u);
+        if (m0 == wv) {
+            // this wave's share of the occupancy hash: site i of the deposit
+            for (uint32_t i = wv * 64 + lane; i < k; i += NSEL * 64) {
+                uint32_t s;
+                if (o == 0) {
+                    uint32_t xx = x + i;
+                    xx = xx >= L ? xx - L : xx;
+                    s = y * L + xx;
+                } else {
+                    uint32_t yy = y + i;
+                    yy = yy >= L ? yy - L : yy;
+                    s = yy * L + x;
+                }
+                occ += mix64(((uint64_t)s << 32) | t);
+            }
+            if (wv == 0) {
+                const LineCut cut = cut_apply(c, spl, slist, sq, sact, sev);
+                bad = bad || cut.bad;
+                if (lane == 0) {
+                    if (o == 0) {
+                        if (cut.n) count_sub(c, y, cut.n);
+                        wchg += cut.nw;
+                    } else {
+                        c.h->jrs = cut.start;
+                        c.h->jn = cut.n;
+                        wchg += cut.n;   // one V word per row of the column
+                    }
+                }
             }
         }
-        // the row-major V bitmap: word blk of every row where some column of
-        // it lost an anchor; the span's bits of it become 0
-        const uint64_t anyh = __ballot(has_ok);
-        if (anyh == 0) continue;
-        const uint64_t spanmask = __ballot(act);
-        const bool whole = spanmask == ~0ull;
-        const uint32_t fl = first_lane(anyh);
-        const uint32_t l0 = bcast(l, fl), h0 = bcast(h, fl);
-        const bool same = __ballot(has_ok && (l != l0 || h != h0)) == 0;
-        const uint32_t lmin = same ? l0 : wave_min32(has_ok ? l : 0xFFFFFFFFu);
-        const uint32_t hmax = same ? h0 : wave_max32(has_ok ? h : 0u);
-        uint64_t *const bm = c.av1;
-        for (uint32_t g = lmin >> 6; g <= (hmax >> 6); ++g) {
-            const int32_t base = (int32_t)(g * 64);
-            uint64_t U;
-            if (same) {
-                U = bit_range((int32_t)l0 > base ? (int32_t)l0 - base : 0,
-                              (int32_t)h0 < base + 63 ? (int32_t)h0 - base : 63);
-            } else {
-                const uint64_t mine = has_ok ? bit_range((int32_t)l > base ? (int32_t)l - base : 0,
-                                                         (int32_t)h < base + 63 ? (int32_t)h - base : 63)
-                                             : 0ull;
-                U = (uint64_t)wave_or32((uint32_t)mine) | ((uint64_t)wave_or32((uint32_t)(mine >> 32)) << 32);
+#pragma unroll
+        for (int f = 0; f < IV_PF; ++f) {
+            const uint32_t m = m0 + (uint32_t)f * NSEL;
+            if (m >= sp.n) break;
+            const uint32_t blk = span_block(sp, m);
+            const uint32_t q = qv[f];
+            const bool act = av[f];
+            const LineCut cut = cut_apply(c, bp, blist, q, act, ev[f]);
+            bad = bad || cut.bad;
+            if (o == 1) {
+                // H row q: its count drops by the anchors removed
+                count_sub_wave(c, act, q, cut.n);
+                wchg += cut.nw;
+                continue;
             }
-            if ((U >> lane) & 1ull) {
-                uint32_t row = blo + (uint32_t)base + lane;
-                row = row >= L ? row - L : row;
-                const uint32_t at = bm_index(c, row, blk);
-                if (whole)
-                    bm[at] = 0ull;
-                else
-                    atomicAnd((unsigned long long *)&bm[at], (unsigned long long)~spanmask);
+            // V column q: rows blo + [l, h] (block-relative) lose an anchor
+            const bool has = act && cut.n != 0;
+            uint32_t l = 0;
+            if (has && cut.n < k) {
+                l = cut.start + L - blo;
+                l = l >= L ? l - L : l;
             }
-            if (lane == 0) wchg += (uint32_t)__popcll(U);
+            const uint32_t h = l + cut.n - 1;
+            // a cut lies inside the block's k rows; anything else is a broken
+            // invariant and is reported, never written
+            const bool in_block = h < k;
+            bad = bad || (has && !in_block);
+            const bool has_ok = has && in_block;
+            if (has_ok) {
+                atomicAdd(&c.dD[l], 1u);
+                atomicAdd(&c.dC[l >> 6], 1u);
+                if (h + 1 < k) {
+                    atomicSub(&c.dD[h + 1], 1u);
+                    atomicSub(&c.dC[(h + 1) >> 6], 1u);
+                }
+            }
+            // the row-major V bitmap: word blk of every row where some column
+            // of it lost an anchor; the span's bits of it become 0.  Lane j
+            // writes rows g*64 + j (block-relative) for the 64-row groups g
+            // in its mask, built from the block's distinct cut ranges
+            uint64_t pend = __ballot(has_ok);
+            if (pend == 0) continue;
+            const uint64_t spanmask = __ballot(act);
+            const bool whole = spanmask == ~0ull;
+            uint64_t M = 0;
+            uint32_t glo_all = 64, ghi_all = 0;
+            while (pend) {
+                const uint32_t f = first_lane(pend);
+                const uint32_t lf = bcast(l, f), hf = bcast(h, f);
+                pend &= ~__ballot(has_ok && l == lf && h == hf);
+                // group g holds row g*64 + lane inside [lf, hf] for
+                // ceil((lf - lane) / 64) <= g <= floor((hf - lane) / 64)
+                const int32_t a = ((int32_t)lf - (int32_t)lane + 63) >> 6;
+                const int32_t b = ((int32_t)hf - (int32_t)lane) >> 6;
+                M |= bit_range(a, b);
+                glo_all = min(glo_all, lf >> 6);
+                ghi_all = max(ghi_all, hf >> 6);
+            }
+            wchg += (uint32_t)__popcll(M);
+            uint64_t *const bm = c.av1;
+            for (uint32_t g = glo_all; g <= ghi_all; ++g) {
+                if ((M >> g) & 1ull) {
+                    uint32_t row = blo + g * 64 + lane;
+                    row = row >= L ? row - L : row;
+                    const uint32_t at = bm_index(c, row, blk);
+                    if (whole)
+                        gst64(&bm[at], 0ull);
+                    else
+                        gand64(&bm[at], ~spanmask);
+                }
+            }
         }
     }
     if (__ballot(bad) && lane == 0) c.h->status = kErrSelect;
+    if (acc) {
+        const uint64_t t1 = tick();
+        if (lane == 0) acc[kAccIvCut] += t1 - pt;
+        pt = t1;
+    }
     sel_barrier<NSEL>(c, passed);
+    if (acc) {
+        const uint64_t t1 = tick();
+        if (lane == 0) acc[kAccIvMeet] += t1 - pt;
+        pt = t1;
+    }
     // ---- phase two
     if (o == 0) {
         // V rows blo + i, i < k: the counts drop by the number of columns
@@ -1039,9 +1124,10 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
             uint32_t row = jrs + i;
             row = row >= L ? row - L : row;
             count_sub_wave(c, act, L + row, 1u);
-            if (act) atomicAnd((unsigned long long *)&bm[bm_index(c, row, x >> 6)], (unsigned long long)~bit);
+            if (act) gand64(&bm[bm_index(c, row, x >> 6)], ~bit);
         }
     }
+    if (acc && lane == 0) acc[kAccIvRows] += tick() - pt;
 }
 
 // Words a lane holds of one bitmap row: lane, lane+64, ... (ROWW of them;
@@ -1287,7 +1373,7 @@ __device__ __forceinline__ bool pick_row(const Ctx &c, uint32_t R, uint32_t rin,
     if (c.interval && R < c.L) {
         const uint32_t lane = lane_id();
         const uint32_t nS = num_buckets(c.L, c.k);
-        const uint32_t E = lane < nS ? c.hb[lane * c.lp() + R] : kNoSeg;
+        const uint32_t E = lane < nS ? gld32(&c.hb[lane * c.lp() + R]) : kNoSeg;
         const uint32_t len = E == kNoSeg ? 0u : seg_end(E) - seg_start(E) + 1;
         const uint32_t inc = wave_scan(len);
         const uint64_t bal = __ballot(inc > rin);
@@ -1415,8 +1501,8 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         uint64_t ph = prof ? tick() : 0;
         if constexpr (SPARSE) {
             if (c.interval) {
-                hash_step();
-                interval_clear<NSEL>(c, o, y, x, 0, wchg, passed);
+                seqh += mix64(((uint64_t)t << 32) | P);   // the sites' hash is split over the waves
+                interval_clear<NSEL>(c, o, y, x, t, 0, wchg, occ, passed, prof ? acc : nullptr);
                 if (prof && lane == 0) acc[kAccProcess] += tick() - ph;
             } else {
                 if constexpr (SPW > 0) {
@@ -1498,6 +1584,9 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         prof_add(c, kProfSpecHits, acc[kAccSpec]);
         prof_add(c, kProfSelHook, acc[kAccHook]);
         prof_add(c, kProfSelProcess, acc[kAccProcess]);
+        prof_add(c, kProfIvCut, acc[kAccIvCut]);
+        prof_add(c, kProfIvMeet, acc[kAccIvMeet]);
+        prof_add(c, kProfIvRows, acc[kAccIvRows]);
     }
     occ = wave_sum64(occ);
     uint32_t wsum = wave_sum32(wchg);
@@ -1520,6 +1609,7 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
     const uint32_t lane = lane_id();
     __builtin_amdgcn_s_setprio(2);
     uint32_t wchg = 0;
+    uint64_t occ = 0;       // this wave's share of the occupancy hash (interval clear)
     uint32_t passed = 0;    // mid-step barriers of the interval clear
     uint32_t g = c.h->t0;   // clear requests are numbered by step
     for (;;) {
@@ -1543,7 +1633,7 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
         uint32_t x = rem - y * c.L;
         if constexpr (SPARSE) {
             if (c.interval)
-                interval_clear<NSEL>(c, o, y, x, wv, wchg, passed);
+                interval_clear<NSEL>(c, o, y, x, g - 1, wv, wchg, occ, passed);
             else
                 sparse_clear<CAP>(c, make_clear(c, o, y, x), wv, NSEL, wchg);
         } else {
@@ -1553,7 +1643,11 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
         if (lane == 0) atomicAdd(&c.h->clr_done, 1u);
     }
     uint32_t wsum = wave_sum32(wchg);
-    if (lane == 0) atomicAdd(&c.h->wchg, (unsigned long long)wsum);
+    occ = wave_sum64(occ);
+    if (lane == 0) {
+        atomicAdd(&c.h->wchg, (unsigned long long)wsum);
+        if (occ) atomicAdd(&c.h->occ, (unsigned long long)occ);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2783,7 +2877,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             h->lab_stop = st->lab_stop;
             h->stop = 0;
             h->ncon[0] = h->ncon[1] = h->ncon[2] = 0;
-            for (int q = 0; q < 7; ++q) h->sel_acc[q] = 0;
+            for (int q = 0; q < 10; ++q) h->sel_acc[q] = 0;
         }
     } else {
         // ---- initial state (Sec. II.A): all placements free; all sites
@@ -2867,7 +2961,7 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
             h->lab_stop = 0;
             h->stop = stop;
             h->ncon[0] = h->ncon[1] = h->ncon[2] = 0;
-            for (int q = 0; q < 7; ++q) h->sel_acc[q] = 0;
+            for (int q = 0; q < 10; ++q) h->sel_acc[q] = 0;
         }
     }
     if (SPARSE && c.interval) {

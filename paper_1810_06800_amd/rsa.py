@@ -30,7 +30,7 @@ OPT_MODE, OPT_TILE, OPT_GRAPH, OPT_SLOTS, OPT_PROFILE = 1, 2, 3, 4, 5
 PROFILE_SLOTS = ("init", "sel_total", "sel_ring", "sel_select", "sel_clear", "lab_total", "lab_idle",
                  "lab_map", "lab_gather", "lab_resolve", "lab_merge", "lab_writeback",
                  "lab_batches", "lab_edges", "lab_flushes", "steps", "spec_hits", "sel_hook",
-                 "sel_process")
+                 "sel_process", "iv_cut", "iv_meet", "iv_rows")
 MODE_BATCHED, MODE_PLAIN = 0, 1
 
 # Symbols declared in include/rsa.h.
