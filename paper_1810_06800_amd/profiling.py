@@ -8,9 +8,15 @@ Commands (from the repository root):
       byte counters; run it under ``rocprofv3 --pmc FETCH_SIZE`` and again
       under ``rocprofv3 --pmc WRITE_SIZE``
 
-  python -m paper_1810_06800_amd.profiling trace-summary OUT_DIR --title T --cmd C
+  python -m paper_1810_06800_amd.profiling trace-summary OUT_DIR --title T --cmd C [--skip N]
       markdown table of a ``rocprofv3 --kernel-trace --stats`` run (calls,
-      average / min / max duration, launch shape) from its output directory
+      average / min / max duration, launch shape) from its output directory;
+      --skip drops each kernel's first N dispatches (the benchmark's warm-up)
+
+  python -m paper_1810_06800_amd.profiling counters DIR [DIR ...] --workload NAME --cmd C
+      markdown table of ``rocprofv3 --pmc`` runs of the workload program: every
+      counter's value for the persistent kernel's dispatch, and the ratios read
+      from them (instruction mix, cycles waiting, L2 hit rate)
 
   python -m paper_1810_06800_amd.profiling traffic --fetch DIR --write DIR --workload NAME --cmd C
       HBM bytes per launch of the persistent kernel from the two counter
@@ -83,27 +89,32 @@ def _find(out_dir: str, pattern: str):
 
 
 def kernel_rows(out_dir: str):
-    """(name, duration_ns, grid, workgroup, lds, vgpr, sgpr) per dispatch."""
+    """(name, duration_ns, grid, workgroup, lds, vgpr, sgpr) per dispatch, in
+    order of start time."""
     rows = []
     for db in _find(out_dir, "*.db"):
         con = sqlite3.connect(db)
+        cols = "name, duration, grid_x, workgroup_x, lds_size, vgpr_count, sgpr_count from kernels"
         try:
-            for r in con.execute("select name, duration, grid_x, workgroup_x, lds_size, vgpr_count, "
-                                 "sgpr_count from kernels"):
-                rows.append(tuple(r))
+            try:
+                cur = con.execute("select start, " + cols)
+            except sqlite3.OperationalError:   # no start column: rows in insertion order
+                cur = con.execute("select rowid, " + cols)
+            rows.extend(tuple(r) for r in cur)
         finally:
             con.close()
-    if rows:
-        return rows
-    for path in _find(out_dir, "*kernel_trace.csv"):
-        with open(path) as f:
-            for r in csv.DictReader(f):
-                rows.append((r["Kernel_Name"], int(r["End_Timestamp"]) - int(r["Start_Timestamp"]),
-                             int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0),
-                             int(r.get("Workgroup_Size_X") or r.get("Workgroup_Size") or 0),
-                             int(r.get("LDS_Block_Size") or r.get("Lds_Size") or 0),
-                             int(r.get("VGPR_Count") or 0), int(r.get("SGPR_Count") or 0)))
-    return rows
+    if not rows:
+        for path in _find(out_dir, "*kernel_trace.csv"):
+            with open(path) as f:
+                for r in csv.DictReader(f):
+                    rows.append((int(r["Start_Timestamp"]), r["Kernel_Name"],
+                                 int(r["End_Timestamp"]) - int(r["Start_Timestamp"]),
+                                 int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0),
+                                 int(r.get("Workgroup_Size_X") or r.get("Workgroup_Size") or 0),
+                                 int(r.get("LDS_Block_Size") or r.get("Lds_Size") or 0),
+                                 int(r.get("VGPR_Count") or 0), int(r.get("SGPR_Count") or 0)))
+    rows.sort(key=lambda r: r[0])
+    return [r[1:] for r in rows]
 
 
 def counter_rows(out_dir: str, counter: str):
@@ -133,17 +144,22 @@ def short(name: str) -> str:
     return name.split("(")[0].replace("void ", "")
 
 
-def trace_summary(out_dir: str, title: str, cmd: str) -> str:
+def trace_summary(out_dir: str, title: str, cmd: str, skip: int = 0) -> str:
     rows = kernel_rows(out_dir)
     if not rows:
         raise SystemExit(f"no kernel trace under {out_dir}")
     groups = {}
     for name, dur, grid, wg, lds, vgpr, sgpr in rows:
-        g = groups.setdefault(short(name), {"d": [], "shape": (grid, wg, lds, vgpr, sgpr)})
-        g["d"].append(dur)
+        g = groups.setdefault(short(name), {"d": [], "n": 0, "shape": (grid, wg, lds, vgpr, sgpr)})
+        g["n"] += 1
+        if g["n"] > skip:   # the first `skip` dispatches of each kernel are the warm-up
+            g["d"].append(dur)
+    groups = {k: g for k, g in groups.items() if g["d"]}
     total = sum(sum(g["d"]) for g in groups.values())
-    out = [f"# {title}", "", "command (from the repository root, one MI355X):", "", f"    {cmd}", "",
-           "| kernel | calls | avg ms | min ms | max ms | total % | grid (threads) | workgroup | LDS B | VGPR | SGPR |",
+    out = [f"# {title}", "", "command (from the repository root, one MI355X):", "", f"    {cmd}", ""]
+    if skip:
+        out += [f"The first {skip} dispatch(es) of each kernel (the warm-up) are left out.", ""]
+    out += ["| kernel | calls | avg ms | min ms | max ms | total % | grid (threads) | workgroup | LDS B | VGPR | SGPR |",
            "|---|---|---|---|---|---|---|---|---|---|---|"]
     for name, g in sorted(groups.items(), key=lambda kv: -sum(kv[1]["d"])):
         d = g["d"]
@@ -175,6 +191,49 @@ def traffic(fetch_dir: str, write_dir: str, workload: str, copy_mib: int, cmd: s
     return out
 
 
+# ratios read from the counter table: (label, numerator, denominator, scale)
+RATIOS = [
+    ("VALU instructions per wave-cycle", "SQ_INSTS_VALU", "SQ_WAVE_CYCLES", 1.0),
+    ("cycles a wave waits (any), % of wave-cycles", "SQ_WAIT_ANY", "SQ_WAVE_CYCLES", 100.0),
+    ("cycles a wave waits for an instruction to issue, % of wave-cycles", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES",
+     100.0),
+    ("cycles with a VALU instruction in flight, % of wave-cycles", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", 100.0),
+    ("cycles with a vector memory instruction in flight, % of wave-cycles", "SQ_ACTIVE_INST_VMEM",
+     "SQ_WAVE_CYCLES", 100.0),
+    ("cycles with an LDS instruction in flight, % of wave-cycles", "SQ_ACTIVE_INST_LDS", "SQ_WAVE_CYCLES", 100.0),
+    ("L2 hit rate, %", "TCC_HIT_sum", "TCC_REQ_sum", 100.0),
+    ("L2 requests per vector memory instruction", "TCC_REQ_sum", "SQ_INSTS_VMEM", 1.0),
+]
+
+
+def counter_summary(dirs, workload: str, cmd: str) -> str:
+    """Every counter of the persistent kernel's dispatch(es) over the given
+    runs, and the ratios of RATIOS that the runs cover."""
+    vals = {}
+    for d in dirs:
+        names = set()
+        for path in _find(d, "*counter_collection.csv"):
+            with open(path) as f:
+                for r in csv.DictReader(f):
+                    names.add(r["Counter_Name"])
+        for name in sorted(names):
+            rows = [r for r in counter_rows(d, name) if PERSISTENT in r[1]]
+            if rows:
+                vals[name] = sum(r[3] for r in rows)
+    if not vals:
+        raise SystemExit("no counters of the persistent kernel found")
+    out = [f"# rsa_persistent counters, workload {workload}", "",
+           "command per pass (from the repository root, one MI355X; COUNTERS is one line of the table's",
+           "passes):", "", f"    {cmd}", "", "| counter | value |", "|---|---|"]
+    for name in sorted(vals):
+        out.append(f"| `{name}` | {vals[name]:.6g} |")
+    out += ["", "| ratio | value |", "|---|---|"]
+    for label, num, den, scale in RATIOS:
+        if num in vals and den in vals and vals[den]:
+            out.append(f"| {label} | {scale * vals[num] / vals[den]:.4g} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_1810_06800_amd.profiling")
     sub = ap.add_subparsers(dest="action", required=True)
@@ -185,6 +244,11 @@ def main(argv=None):
     t.add_argument("out_dir")
     t.add_argument("--title", required=True)
     t.add_argument("--cmd", required=True)
+    t.add_argument("--skip", type=int, default=0)
+    cs = sub.add_parser("counters")
+    cs.add_argument("dirs", nargs="+")
+    cs.add_argument("--workload", required=True)
+    cs.add_argument("--cmd", required=True)
     tr = sub.add_parser("traffic")
     tr.add_argument("--fetch", required=True)
     tr.add_argument("--write", required=True)
@@ -195,7 +259,9 @@ def main(argv=None):
     if a.action == "workload":
         run_workload(a.name, a.copy_mib)
     elif a.action == "trace-summary":
-        sys.stdout.write(trace_summary(a.out_dir, a.title, a.cmd))
+        sys.stdout.write(trace_summary(a.out_dir, a.title, a.cmd, a.skip))
+    elif a.action == "counters":
+        sys.stdout.write(counter_summary(a.dirs, a.workload, a.cmd))
     else:
         print(json.dumps(traffic(a.fetch, a.write, a.workload, a.copy_mib, a.cmd), indent=1))
 

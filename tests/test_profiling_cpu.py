@@ -1,6 +1,7 @@
 """The rocprofv3 summaries in profiling.py, on small synthetic outputs: the
-kernel-trace table from a rocpd-style database, and the traffic figure from
-two counter CSVs scaled by the copy kernel's reading."""
+kernel-trace table from a rocpd-style database (with the warm-up left out),
+the traffic figure from two counter CSVs scaled by the copy kernel's
+reading, and the counter table with its ratios."""
 import csv
 import json
 import os
@@ -60,3 +61,32 @@ def test_trace_summary_from_database(tmp_path):
     cells = [c.strip() for c in row.strip("|").split("|")]
     assert cells[1] == "3" and cells[2] == "38.000" and cells[3] == "36.000" and cells[4] == "40.000"
     assert cells[6:] == ["131072", "128", "31904", "88", "112"]
+
+
+def test_trace_summary_skips_the_warmup_by_start_time(tmp_path):
+    db = tmp_path / "run" / "trace_results.db"
+    db.parent.mkdir()
+    con = sqlite3.connect(str(db))
+    con.execute("create table kernels (start integer, name text, duration integer, grid_x integer, "
+                "workgroup_x integer, lds_size integer, vgpr_count integer, sgpr_count integer)")
+    # inserted out of order: the earliest dispatch (the warm-up) is the slow one
+    for start, d in ((300, 20_000_000), (100, 90_000_000), (200, 10_000_000)):
+        con.execute("insert into kernels values (?, ?, ?, ?, ?, ?, ?, ?)", (start, PERSISTENT, d, 16384, 512, 0, 1, 1))
+    con.commit()
+    con.close()
+    text = profiling.trace_summary(str(tmp_path / "run"), "t", "cmd", skip=1)
+    row = [l for l in text.splitlines() if "rsa_persistent" in l][0]
+    cells = [c.strip() for c in row.strip("|").split("|")]
+    assert cells[1] == "2" and cells[2] == "15.000" and cells[3] == "10.000" and cells[4] == "20.000"
+    assert "left out" in text
+
+
+def test_counter_summary_ratios(tmp_path):
+    write_counters(str(tmp_path / "a"), "SQ_WAVE_CYCLES", [(2, PERSISTENT, 1000.0), (3, COPY, 5.0)])
+    write_counters(str(tmp_path / "b"), "SQ_WAIT_ANY", [(2, PERSISTENT, 250.0)])
+    write_counters(str(tmp_path / "c"), "TCC_HIT_sum", [(2, PERSISTENT, 30.0)])
+    write_counters(str(tmp_path / "d"), "TCC_REQ_sum", [(2, PERSISTENT, 40.0)])
+    text = profiling.counter_summary([str(tmp_path / x) for x in "abcd"], "w", "cmd")
+    assert "| `SQ_WAVE_CYCLES` | 1000 |" in text
+    assert "| cycles a wave waits (any), % of wave-cycles | 25 |" in text
+    assert "| L2 hit rate, % | 75 |" in text
