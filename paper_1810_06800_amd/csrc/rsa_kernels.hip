@@ -66,6 +66,14 @@ __device__ __forceinline__ void gand64(uint64_t *p, uint64_t m)
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// v[i] of four values (i wave-uniform or a constant), without an array
+// indexed at run time (which would live in scratch memory).
+template <class T>
+__device__ __forceinline__ T pick4(uint32_t i, T a, T b, T c, T d)
+{
+    return i == 0 ? a : i == 1 ? b : i == 2 ? c : d;
+}
+
 // LDS-only hand-offs between waves of one workgroup: LDS instructions of a
 // wave execute in issue order, so a compiler-only fence is enough to order a
 // payload before (after) the flag that publishes (consumes) it.
@@ -691,6 +699,7 @@ __device__ __forceinline__ uint32_t seg_end(uint32_t v) { return v >> 16; }
 struct CutPlan {
     uint32_t lo, len, wend;
     uint32_t n0, ja, nj;
+    uint32_t off0, off1, off2, off3;   // list offsets of the touched buckets' entries of line 0
     bool full, wraps, over;
 };
 
@@ -727,17 +736,27 @@ __device__ __forceinline__ CutPlan cut_plan(const Ctx &c, uint32_t lo, uint32_t 
     p.nj = p.n0 + n1;
     p.over = p.nj > 4;
     if (p.over) p.nj = 4;
+    const uint32_t lp = c.lp();
+    p.off0 = plan_bucket(p, 0) * lp;
+    p.off1 = plan_bucket(p, 1) * lp;
+    p.off2 = plan_bucket(p, 2) * lp;
+    p.off3 = plan_bucket(p, 3) * lp;
     return p;
 }
 
 // Read the touched bucket entries of line q (kNoSeg where nothing is read).
+// Every lane loads (an inactive one from line 0, discarded), so the loads
+// need no per-lane branches; entries past the plan are skipped for the wave.
 __device__ __forceinline__ void cut_load(const Ctx &c, const CutPlan &p, const uint32_t *list, uint32_t q, bool act,
                                          uint32_t ev[4])
 {
-    const uint32_t lp = c.lp();
+    const uint32_t *const base = list + (act ? q : 0u);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        ev[i] = (act && (uint32_t)i < p.nj) ? gld32(&list[plan_bucket(p, (uint32_t)i) * lp + q]) : kNoSeg;
+    for (int i = 0; i < 4; ++i) {
+        uint32_t v = kNoSeg;
+        if ((uint32_t)i < p.nj) v = gld32(base + pick4((uint32_t)i, p.off0, p.off1, p.off2, p.off3));
+        ev[i] = act ? v : kNoSeg;
+    }
 }
 
 // Remove the available anchors inside the plan's range from line q, whose
@@ -746,7 +765,7 @@ __device__ __forceinline__ void cut_load(const Ctx &c, const CutPlan &p, const u
 __device__ __forceinline__ LineCut cut_apply(const Ctx &c, const CutPlan &p, uint32_t *list, uint32_t q, bool act,
                                              const uint32_t ev[4])
 {
-    const uint32_t lp = c.lp(), lo = p.lo, len = p.len, wend = p.wend;
+    const uint32_t lo = p.lo, len = p.len, wend = p.wend;
     LineCut r;
     r.n = 0;
     r.nw = 0;
@@ -811,7 +830,7 @@ __device__ __forceinline__ LineCut cut_apply(const Ctx &c, const CutPlan &p, uin
             prev_e = (uint32_t)b;
         }
         const uint32_t nv = keep ? ((uint32_t)ks | ((uint32_t)ke << 16)) : kNoSeg;
-        if (nv != E) gst32(&list[plan_bucket(p, (uint32_t)i) * lp + q], nv);
+        if (nv != E) gst32(&list[pick4((uint32_t)i, p.off0, p.off1, p.off2, p.off3) + q], nv);
     }
     return r;
 }
@@ -878,13 +897,19 @@ __device__ __forceinline__ void count_sub_wave(const Ctx &c, bool act, uint32_t 
 // The selecting waves meet once per step between the two phases of the
 // interval clear (LDS arrivals counter; every wave passes the same number).
 template <int NSEL>
-__device__ __forceinline__ void sel_barrier(const Ctx &c, uint32_t &passed)
+__device__ __forceinline__ void sel_barrier(const Ctx &c, uint32_t &passed, bool selecting)
 {
     if constexpr (NSEL > 1) {
         ++passed;
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (lane_id() == 0) atomicAdd(&c.h->bar, 1u);
+        // a wave that waits yields its SIMD's issue slots to the waves still working
+        __builtin_amdgcn_s_setprio(0);
         while (lds_load(&c.h->bar) < passed * (uint32_t)NSEL) __builtin_amdgcn_s_sleep(1);
+        if (selecting)
+            __builtin_amdgcn_s_setprio(3);
+        else
+            __builtin_amdgcn_s_setprio(2);
     }
 }
 
@@ -956,8 +981,6 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
     const uint32_t sq = o ? x : y;
     const CutPlan spl = cut_plan(c, o ? yb : xb, strip);
     const bool sact = wv == 0 && lane == 0;
-    uint32_t sev[4];
-    cut_load(c, spl, slist, sq, sact, sev);
     // the crossing lines: for H, V columns x .. x+k-1 lose rows [y-k+1, y];
     // for V, H rows y .. y+k-1 lose columns [x-k+1, x]; 64-line blocks
     // round-robin over the waves, up to IV_PF of them read at once
@@ -966,11 +989,14 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
     uint32_t *const blist = o ? c.hb : c.vb;
     const uint32_t blo = o ? xb : yb;
     const CutPlan bp = cut_plan(c, blo, k);
-    // (every wave passes once, for its share of the hash, if it has no block)
-    for (uint32_t m0 = wv; m0 == wv || m0 < sp.n; m0 += NSEL * IV_PF) {
-        uint32_t ev[IV_PF][4];
-        uint32_t qv[IV_PF];
-        bool av[IV_PF];
+    // Every read of a pass is issued before any is used.  The first pass is
+    // written out of the loop, and the deposit's own line is read after its
+    // block reads: a wait for that read placed ahead of them (the compiler
+    // moves the own line's arithmetic up) would cost a second round trip.
+    uint32_t ev[IV_PF][4];
+    uint32_t qv[IV_PF];
+    bool av[IV_PF];
+    const auto prefetch = [&](uint32_t m0) {
 #pragma unroll
         for (int f = 0; f < IV_PF; ++f) {
             const uint32_t m = m0 + (uint32_t)f * NSEL;
@@ -979,36 +1005,8 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
             qv[f] = q;
             cut_load(c, bp, blist, q, av[f], ev[f]);
         }
-        if (m0 == wv) {
-            // this wave's share of the occupancy hash: site i of the deposit
-            for (uint32_t i = wv * 64 + lane; i < k; i += NSEL * 64) {
-                uint32_t s;
-                if (o == 0) {
-                    uint32_t xx = x + i;
-                    xx = xx >= L ? xx - L : xx;
-                    s = y * L + xx;
-                } else {
-                    uint32_t yy = y + i;
-                    yy = yy >= L ? yy - L : yy;
-                    s = yy * L + x;
-                }
-                occ += mix64(((uint64_t)s << 32) | t);
-            }
-            if (wv == 0) {
-                const LineCut cut = cut_apply(c, spl, slist, sq, sact, sev);
-                bad = bad || cut.bad;
-                if (lane == 0) {
-                    if (o == 0) {
-                        if (cut.n) count_sub(c, y, cut.n);
-                        wchg += cut.nw;
-                    } else {
-                        c.h->jrs = cut.start;
-                        c.h->jn = cut.n;
-                        wchg += cut.n;   // one V word per row of the column
-                    }
-                }
-            }
-        }
+    };
+    const auto apply = [&](uint32_t m0) {
 #pragma unroll
         for (int f = 0; f < IV_PF; ++f) {
             const uint32_t m = m0 + (uint32_t)f * NSEL;
@@ -1081,6 +1079,45 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
                 }
             }
         }
+    };
+    // shares: block m goes to wave (m + 1) % NSEL, so the selecting wave, which
+    // also cuts the deposit's own line, has the fewest blocks
+    const uint32_t w0 = (wv + NSEL - 1) % NSEL;
+    prefetch(w0);
+    uint32_t sev[4];
+    cut_load(c, spl, slist, sq, sact, sev);
+    // this wave's share of the occupancy hash: site i of the deposit
+    for (uint32_t i = w0 * 64 + lane; i < k; i += NSEL * 64) {
+        uint32_t s;
+        if (o == 0) {
+            uint32_t xx = x + i;
+            xx = xx >= L ? xx - L : xx;
+            s = y * L + xx;
+        } else {
+            uint32_t yy = y + i;
+            yy = yy >= L ? yy - L : yy;
+            s = yy * L + x;
+        }
+        occ += mix64(((uint64_t)s << 32) | t);
+    }
+    if (wv == 0) {
+        const LineCut cut = cut_apply(c, spl, slist, sq, sact, sev);
+        bad = bad || cut.bad;
+        if (lane == 0) {
+            if (o == 0) {
+                if (cut.n) count_sub(c, y, cut.n);
+                wchg += cut.nw;
+            } else {
+                c.h->jrs = cut.start;
+                c.h->jn = cut.n;
+                wchg += cut.n;   // one V word per row of the column
+            }
+        }
+    }
+    apply(w0);
+    for (uint32_t m0 = w0 + NSEL * IV_PF; m0 < sp.n; m0 += NSEL * IV_PF) {
+        prefetch(m0);
+        apply(m0);
     }
     if (__ballot(bad) && lane == 0) c.h->status = kErrSelect;
     if (acc) {
@@ -1088,7 +1125,7 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
         if (lane == 0) acc[kAccIvCut] += t1 - pt;
         pt = t1;
     }
-    sel_barrier<NSEL>(c, passed);
+    sel_barrier<NSEL>(c, passed, wv == 0);
     if (acc) {
         const uint64_t t1 = tick();
         if (lane == 0) acc[kAccIvMeet] += t1 - pt;
@@ -1103,7 +1140,7 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
         const uint32_t cv = lane < nC ? lds_peek(&c.dC[lane]) : 0u;
         const uint32_t cinc = wave_scan(cv);
         const uint32_t cex = cinc - cv;
-        for (uint32_t m = wv; m < nC; m += NSEL) {
+        for (uint32_t m = w0; m < nC; m += NSEL) {
             const uint32_t i = m * 64 + lane;
             const bool act = i < k;
             const uint32_t dv = act ? lds_peek(&c.dD[i]) : 0u;
@@ -1118,7 +1155,7 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
         const uint32_t jrs = lds_peek(&c.h->jrs), jn = lds_peek(&c.h->jn);
         uint64_t *const bm = c.av1;
         const uint64_t bit = 1ull << (x & 63u);
-        for (uint32_t m = wv; m * 64 < jn; m += NSEL) {
+        for (uint32_t m = w0; m * 64 < jn; m += NSEL) {
             const uint32_t i = m * 64 + lane;
             const bool act = i < jn;
             uint32_t row = jrs + i;
@@ -1409,7 +1446,7 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
     // window covers too few rows to hit often, so it is left out
     constexpr int SPW = ROWW == 1 ? 2 : 0;
     const uint32_t lane = lane_id();
-    __builtin_amdgcn_s_setprio(2);   // latency-critical chain first on a shared SIMD
+    __builtin_amdgcn_s_setprio(3);   // latency-critical chain first on a shared SIMD
     const uint32_t L = c.L, k = c.k;
     const uint32_t t_begin = c.h->t0;
     // with STOP, selection ends before step h->stop as if the lattice jammed there
@@ -1532,7 +1569,9 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
         if (NSEL > 1) {
             // helpers' bitmap stores must be visible before the next select
             uint32_t want = t1 * (NSEL - 1);
+            __builtin_amdgcn_s_setprio(0);
             while (lds_load(&c.h->clr_done) < want) __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_s_setprio(3);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
         if (SPARSE && c.interval && o == 0) {
@@ -1615,6 +1654,8 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
     for (;;) {
         uint32_t gen;
         bool stop = false;
+        // waiting for the next clear: the selecting wave's select goes first
+        __builtin_amdgcn_s_setprio(0);
         for (;;) {
             gen = lds_load(&c.h->clr_gen);
             if (gen > g) break;
@@ -1624,6 +1665,7 @@ __device__ __forceinline__ void helper(Ctx &c, uint32_t wv)
             }
             __builtin_amdgcn_s_sleep(1);
         }
+        __builtin_amdgcn_s_setprio(2);
         if (stop) break;
         g = gen;
         uint32_t P = uniform(lds_peek(&c.h->cur_p));
