@@ -214,10 +214,11 @@ int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, int census, uint
     return nb * c->cus;
 }
 
-bool use_interval(uint32_t L, uint32_t k, int tile, size_t lds_max)
+bool use_interval(uint32_t L, uint32_t k, int tile) { return tile_sparse(tile) && interval_shape(L, k); }
+
+bool interval_in_lds(uint32_t L, uint32_t k, size_t lds_max)
 {
-    return tile_sparse(tile) && k <= kIntervalMaxK && has_buckets(L, k) &&
-           (size_t)lds_layout(L).total + interval_lds_bytes(k) + 64 <= lds_max;
+    return (size_t)lds_layout(L).total + interval_lds_bytes(k) + 64 <= lds_max;
 }
 
 bool use_compressed(uint32_t L, uint32_t k, int tile)
@@ -230,7 +231,8 @@ size_t sample_slab(uint32_t L, uint32_t k, int tile) { return slab_layout(L, k, 
 
 uint32_t sample_lds(uint32_t L, uint32_t k, int tile, size_t lds_max)
 {
-    return lds_layout(L).total + (use_interval(L, k, tile, lds_max) ? interval_lds_bytes(k) : 0u);
+    return lds_layout(L).total +
+           (use_interval(L, k, tile) && interval_in_lds(L, k, lds_max) ? interval_lds_bytes(k) : 0u);
 }
 
 DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile, size_t lds_max)
@@ -250,7 +252,8 @@ DevDesc make_dev_desc(const rsa_sample_t &s, uint32_t out, int tile, size_t lds_
     d.fwd = make_fastdiv(d.wd);
     d.fwp = make_fastdiv(padded_words(s.L));
     d.fB = make_fastdiv(s.k + 1);
-    d.interval = use_interval(s.L, s.k, tile, lds_max) ? 1u : 0u;
+    d.interval = use_interval(s.L, s.k, tile) ? 1u : 0u;
+    d.ivg = d.interval && !interval_in_lds(s.L, s.k, lds_max) ? 1u : 0u;
     d.compressed = use_compressed(s.L, s.k, tile) ? 1u : 0u;
     d.tile = (uint32_t)tile;
     d.sparse = (uint32_t)tile_sparse(tile);

@@ -45,7 +45,7 @@ __host__ __device__ inline uint32_t summary_words(uint32_t L) { return (padded_w
 // A bucket entry is start | end << 16, or kNoSeg.
 constexpr uint32_t kNoSeg = 0xFFFFFFFFu;
 constexpr uint32_t kMaxBuckets = 64;       // one wave reads a whole line
-constexpr uint32_t kIntervalMaxK = 4096;   // difference counts of a k-row block in LDS
+constexpr uint32_t kIntervalMaxK = 4096;   // difference counts of a k-row block
 __host__ __device__ inline uint32_t num_buckets(uint32_t L, uint32_t k) { return (L + k) / (k + 1); }
 __host__ __device__ inline bool has_buckets(uint32_t L, uint32_t k) { return num_buckets(L, k) <= kMaxBuckets; }
 // Compressed lattice (Sec. II.E stores a few bits per site instead of the
@@ -66,10 +66,14 @@ __host__ __device__ inline uint32_t hash_slots(uint32_t L, uint32_t k)
     return c;
 }
 
-// LDS after the common layout for the interval clear: per-row difference
-// counts of a k-row block, and their sums over 64 rows.
+// The interval clear's per-row difference counts of a k-row block and their
+// sums over 64 rows: in LDS after the common layout when they fit, else in
+// the slab, two sets used by alternate steps (a set is cleared during its
+// step and reused two steps later, after a wait that orders the clearing
+// stores before the next use).
 __host__ __device__ inline uint32_t interval_diff_words(uint32_t k) { return (k + 1 + 3) & ~3u; }
 __host__ __device__ inline uint32_t interval_lds_bytes(uint32_t k) { return 4 * (interval_diff_words(k) + 68); }
+__host__ __device__ inline bool interval_shape(uint32_t L, uint32_t k) { return k <= kIntervalMaxK && has_buckets(L, k); }
 
 // One sample as the kernels see it.
 struct DevDesc {
@@ -85,7 +89,7 @@ struct DevDesc {
     uint32_t sparse;      // clear mode: 0 dense, 1 sparse (summary bits or intervals)
     uint32_t interval;    // sparse mode by anchor intervals (1) or by summary bits (0)
     uint32_t compressed;  // site map replaced by occupancy / anchor bitmaps (1)
-    uint32_t pad2;
+    uint32_t ivg;         // interval clear with its difference counts in the slab (1) or in LDS (0)
     uint64_t slab;        // the sample's own slab, or 0 = the workgroup's slab
     FastDiv fL;        // division by L
     FastDiv fk;        // division by k
@@ -171,9 +175,11 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t L)
 //                       along rows (ovr tiled) and along columns (ohc tiled)
 //   ahr, avc            H anchors along rows, V anchors along columns
 //   khash               placement index + 1 | deposit number << 32, per slot
+//   ivd                 two sets of the interval clear's difference counts
+//                       (used when they do not fit LDS)
 struct SlabLayout {
     size_t avail0, avail1, sum0, sum1, map, node, kmer, state, hb, vb;
-    size_t ohr, ovr, ohc, ovc, ahr, avc, khash, total;
+    size_t ohr, ovr, ohc, ovc, ahr, avc, khash, ivd, total;
 };
 
 // Status values of a time-sliced run besides 0 and the negative errors:
@@ -241,6 +247,7 @@ __host__ __device__ inline SlabLayout slab_layout(uint32_t L, uint32_t k, bool c
     const size_t nb = has_buckets(L, k) ? (size_t)num_buckets(L, k) * lp * 4 : 0;
     s.hb = off;     off = align256(off + nb);
     s.vb = off;     off = align256(off + nb);
+    s.ivd = off;    off = align256(off + (interval_shape(L, k) ? (size_t)8 * (interval_diff_words(k) + 68) : 0));
     s.total = off;
     return s;
 }

@@ -246,8 +246,9 @@ struct Ctx {
     uint32_t *h_key;    // root hash: keys, then values (kHash each)
     // interval clear (long k-mers): anchor-interval buckets of H rows and V
     // columns in the slab, per-row difference counts of a block and their
-    // 64-row sums in LDS
-    uint32_t interval;
+    // 64-row sums in LDS, or (ivg) two sets of them in the slab, set t & 1
+    // at dD + (t & 1) * ivstride for step t
+    uint32_t interval, ivg, ivstride;
     uint32_t *hb, *vb;
     uint32_t *dD, *dC;
     FastDiv fB;
@@ -967,6 +968,9 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
     uint64_t pt = acc ? tick() : 0;
     const uint32_t L = c.L, k = c.k, lane = lane_id();
     const uint32_t strip = 2 * k - 1 < L ? 2 * k - 1 : L;
+    // this step's difference counts
+    uint32_t *const dD = c.dD + (t & 1u) * c.ivstride;
+    uint32_t *const dC = dD + interval_diff_words(k);
     uint32_t xb = x + L - (k - 1);
     xb = xb >= L ? xb - L : xb;
     uint32_t yb = y + L - (k - 1);
@@ -1036,11 +1040,11 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
             bad = bad || (has && !in_block);
             const bool has_ok = has && in_block;
             if (has_ok) {
-                atomicAdd(&c.dD[l], 1u);
-                atomicAdd(&c.dC[l >> 6], 1u);
+                atomicAdd(&dD[l], 1u);
+                atomicAdd(&dC[l >> 6], 1u);
                 if (h + 1 < k) {
-                    atomicSub(&c.dD[h + 1], 1u);
-                    atomicSub(&c.dC[(h + 1) >> 6], 1u);
+                    atomicSub(&dD[h + 1], 1u);
+                    atomicSub(&dC[(h + 1) >> 6], 1u);
                 }
             }
             // the row-major V bitmap: word blk of every row where some column
@@ -1125,6 +1129,9 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
         if (lane == 0) acc[kAccIvCut] += t1 - pt;
         pt = t1;
     }
+    // counts in the slab: this wave's atomics (and its clearing of the set
+    // two steps back) are done at L2 before the waves meet
+    if (c.ivg) __builtin_amdgcn_s_waitcnt(0);
     sel_barrier<NSEL>(c, passed, wv == 0);
     if (acc) {
         const uint64_t t1 = tick();
@@ -1137,18 +1144,46 @@ __device__ __forceinline__ void interval_clear(const Ctx &c, uint32_t o, uint32_
         // whose cut covers row i (difference counts, their 64-row sums give
         // each block's carry)
         const uint32_t nC = (k + 63) >> 6;   // <= 64
-        const uint32_t cv = lane < nC ? lds_peek(&c.dC[lane]) : 0u;
-        const uint32_t cinc = wave_scan(cv);
-        const uint32_t cex = cinc - cv;
-        for (uint32_t m = w0; m < nC; m += NSEL) {
+        const auto row_group = [&](uint32_t m, uint32_t dv, uint32_t cex) {
             const uint32_t i = m * 64 + lane;
             const bool act = i < k;
-            const uint32_t dv = act ? lds_peek(&c.dD[i]) : 0u;
-            if (act) c.dD[i] = 0u;
-            const uint32_t dcount = wave_scan(dv) + bcast(cex, m);
+            if (act) dD[i] = 0u;
+            const uint32_t dcount = wave_scan(act ? dv : 0u) + bcast(cex, m);
             uint32_t row = blo + i;
             row = row >= L ? row - L : row;
             count_sub_wave(c, act, L + row, dcount);
+        };
+        if (!c.ivg) {
+            const uint32_t cv = lane < nC ? lds_peek(&dC[lane]) : 0u;
+            const uint32_t cex = wave_scan(cv) - cv;
+            for (uint32_t m = w0; m < nC; m += NSEL) {
+                const uint32_t i = m * 64 + lane;
+                row_group(m, i < k ? lds_peek(&dD[i]) : 0u, cex);
+            }
+        } else {
+            // counts in the slab: up to 8 of the wave's row groups read at
+            // once (every lane reads an entry that exists; out-of-range ones
+            // are masked where they are used)
+            const auto ld = [](const uint32_t *p) {
+                return __hip_atomic_load((const gmem<uint32_t> *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            };
+            const uint32_t cv0 = ld(&dC[lane]);
+            const uint32_t cv = lane < nC ? cv0 : 0u;
+            const uint32_t cex = wave_scan(cv) - cv;
+            for (uint32_t m0 = w0; m0 < nC; m0 += 8 * NSEL) {
+                uint32_t dv[8];
+#pragma unroll
+                for (uint32_t u = 0; u < 8; ++u) {
+                    const uint32_t i = (m0 + u * NSEL) * 64 + lane;
+                    dv[u] = ld(&dD[i < k ? i : 0u]);
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < 8; ++u) {
+                    const uint32_t m = m0 + u * NSEL;
+                    if (m >= nC) break;
+                    row_group(m, dv[u], cex);
+                }
+            }
         }
     } else {
         // V rows of the deposit's own column that lost their anchor at x
@@ -1575,8 +1610,9 @@ __device__ __forceinline__ void selector(Ctx &c, uint64_t deadline)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
         if (SPARSE && c.interval && o == 0) {
-            // every wave is past this step's block sums: clear them for the next
-            if (lane < ((k + 63) >> 6)) c.dC[lane] = 0u;
+            // every wave is past this step's block sums: clear them for the
+            // next use of this set
+            if (lane < ((k + 63) >> 6)) c.dC[(t & 1u) * c.ivstride + lane] = 0u;
         }
         if (prof) {
             uint64_t p1 = tick();
@@ -2828,7 +2864,9 @@ __device__ __forceinline__ void carve(Ctx &c, const DevDesc &d, uint8_t *slab, u
     c.interval = d.interval;
     c.hb = (uint32_t *)(slab + s.hb);
     c.vb = (uint32_t *)(slab + s.vb);
-    c.dD = (uint32_t *)(lds + l.total);
+    c.ivg = d.ivg;
+    c.ivstride = d.ivg ? interval_diff_words(d.k) + 68 : 0u;
+    c.dD = d.ivg ? (uint32_t *)(slab + s.ivd) : (uint32_t *)(lds + l.total);
     c.dC = c.dD + interval_diff_words(d.k);
     c.fB = d.fB;
     c.compressed = d.compressed;
@@ -3007,7 +3045,9 @@ __device__ __forceinline__ void run_sample(const KernelArgs &a, const DevDesc &d
         }
     }
     if (SPARSE && c.interval) {
-        for (uint32_t i = tid; i < interval_diff_words(c.k) + 68; i += NT) c.dD[i] = 0u;
+        const uint32_t n = (c.ivg ? 2u : 1u) * (interval_diff_words(c.k) + 68);
+        for (uint32_t i = tid; i < n; i += NT) c.dD[i] = 0u;
+        if (c.ivg) __builtin_amdgcn_s_waitcnt(0);   // slab stores done before any step's atomics
     }
     if (tid == 0) c.h->bar = 0;
     __syncthreads();

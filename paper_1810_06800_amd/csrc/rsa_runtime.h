@@ -136,10 +136,12 @@ void give_pinned(rsa_ctx *c, void *p, size_t bytes);
 // Workgroups of a schedule's kernel resident on the whole device at once.
 int resident_blocks(rsa_ctx *c, int tile, int wide, int sparse, int census, uint32_t lds);
 // Whether a sample of a sparse-clear tile runs the interval clear: k up to
-// kIntervalMaxK, at most kMaxBuckets buckets per line, and its difference
-// counts fit the workgroup's LDS beside the row counts.  Otherwise the sparse
-// clear by summary bits.
-bool use_interval(uint32_t L, uint32_t k, int tile, size_t lds_max);
+// kIntervalMaxK and at most kMaxBuckets buckets per line.  Otherwise the
+// sparse clear by summary bits.
+bool use_interval(uint32_t L, uint32_t k, int tile);
+// Whether the interval clear's difference counts fit the workgroup's LDS
+// beside the row counts (else they live in the slab).
+bool interval_in_lds(uint32_t L, uint32_t k, size_t lds_max);
 // Whether a sample keeps the compressed lattice (occupancy and anchor bitmaps
 // instead of the int32 site map): sparse-clear tiles with k >= kCompressMinK.
 bool use_compressed(uint32_t L, uint32_t k, int tile);

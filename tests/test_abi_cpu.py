@@ -71,8 +71,12 @@ def test_footprint_matches_layout(rsa):
         while slots < 2 * (L * L // k + 1):
             slots *= 2
         bitmaps = 6 * a(((L + 63) // 64) * ((L + 15) // 16) * 16 * 8) + a(8 * slots) if compressed else 0
+        # shapes the interval clear takes (k <= 4096, buckets): two sets of its
+        # k + 1 difference counts (rounded to 4) and 68 sums, for lattices
+        # whose LDS cannot hold them
+        diffs = 2 * 4 * (((k + 1 + 3) // 4) * 4 + 68) if (k <= 4096 and nb <= 64) else 0
         return (a(lp * wp * 8) * 2 + summary * 2 + site_map + a(16 * cap) + a(4 * cap)
-                + a(256 + counts) + buckets + bitmaps)
+                + a(256 + counts) + buckets + bitmaps + a(diffs))
 
     for L, k in [(1, 1), (5, 3), (64, 8), (1024, 64), (16384, 1024), (32768, 4096), (16384, 2),
                  (130, 1), (4096, 63), (4097, 4097), (600, 512), (1000, 511)]:
