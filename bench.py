@@ -5,8 +5,7 @@ One step = one batch of the whole hot path (init, draw, select, deposit and
 clear, contacts + union-find + wrap check, result) over the workload, from
 descriptors in host memory to results back; every input lives in HBM while
 the kernels run.  The default workload is L = 16384, k = 1024, 32 samples
-(seed 4): the largest single-GPU configuration, on which the HBM target is
-set.  ``--workload`` names the others (plain_small, plain_scale, mixed_batch,
+(seed 4), the largest single-GPU configuration of the measured set.  ``--workload`` names the others (plain_small, plain_scale, mixed_batch,
 large_32k).
 
 The JSON line also carries
@@ -77,8 +76,8 @@ def cpu_baseline(descs, gpu_results, budget_s: float):
     fills the rest.  Throughput is deposits over the wall time of both."""
     import oracle
 
-    # the host cores this process may use, at most 16: a GPU box allots 16
-    # host cores to each GPU, so that is the whole share of one GPU
+    # the host cores this process may use, at most 16: the host's share of
+    # cores per GPU on the machines this runs on
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
     n1 = min(threads, len(descs))
     t0 = time.perf_counter()
@@ -115,7 +114,7 @@ def cpu_model() -> str:
 
 def copy_rate_gbs(mib: int = 4096, reps: int = 5) -> float:
     """Streaming rate of a plain device copy (read + write bytes over its
-    HIP-event time, best of reps): the achievable HBM rate on this machine."""
+    HIP-event time, best of reps): the achievable HBM rate on this device."""
     import torch
 
     n = mib * (1 << 20) // 4
@@ -135,7 +134,7 @@ def copy_rate_gbs(mib: int = 4096, reps: int = 5) -> float:
     return 2 * mib * (1 << 20) / (best * 1e-3) / 1e9
 
 
-def survey_bytes(descs, results) -> int:
+def roofline_bytes(descs, results) -> int:
     """Algorithmic bytes of the batch in the per-sample model described at the
     top: the library's alg_bytes plus 4L^2 for the final occupancy scan and
     48 more bytes of union-find records per deposit."""
@@ -243,7 +242,7 @@ def main():
     deposits = int(results["n_jam"].sum())
     alg_bytes = int(results["alg_bytes"].sum())
     results = [{f: r[f].item() for f in results.dtype.names} for r in results]   # for the checks below
-    model_bytes = survey_bytes(descs, results)
+    model_bytes = roofline_bytes(descs, results)
     value = deposits * args.steps / wall
     avg_ms = sum(kernel_ms) / len(kernel_ms)
     achieved = model_bytes / (avg_ms * 1e-3) / 1e9
