@@ -260,9 +260,13 @@ const char *rsa_last_error(rsa_ctx *ctx);
  *   RSA_OPT_PROFILE 0 (default); 1 = later batches record per-sample phase
  *                  counters (device wall-clock ticks), read by
  *                  rsa_batch_profile; results are unchanged
+ *   RSA_OPT_IV_SLAB 0 (default); 1 = diagnostic: samples on the interval
+ *                  clear keep its difference counts in the slab even where
+ *                  they fit LDS (the layout large lattices use); results are
+ *                  unchanged
  * Unknown options or values: RSA_EINVAL. */
 enum rsa_option { RSA_OPT_MODE = 1, RSA_OPT_TILE = 2, RSA_OPT_GRAPH = 3, RSA_OPT_SLOTS = 4,
-                  RSA_OPT_PROFILE = 5 };
+                  RSA_OPT_PROFILE = 5, RSA_OPT_IV_SLAB = 6 };
 enum rsa_mode { RSA_MODE_BATCHED = 0, RSA_MODE_PLAIN = 1 };
 int rsa_set_option(rsa_ctx *ctx, int option, int64_t value);
 int rsa_get_option(rsa_ctx *ctx, int option, int64_t *value);

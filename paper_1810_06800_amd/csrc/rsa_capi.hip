@@ -221,6 +221,8 @@ bool interval_in_lds(uint32_t L, uint32_t k, size_t lds_max)
     return (size_t)lds_layout(L).total + interval_lds_bytes(k) + 64 <= lds_max;
 }
 
+size_t interval_lds_max(const rsa_ctx *c) { return c->opt_ivslab ? 0 : c->lds_max; }
+
 bool use_compressed(uint32_t L, uint32_t k, int tile)
 {
     (void)L;
@@ -436,6 +438,10 @@ int rsa_set_option(rsa_ctx *c, int option, int64_t value)
         if (value != 0 && value != 1) return fail(c, RSA_EINVAL, "bad profile flag");
         c->opt_prof = value;
         return RSA_OK;
+    case RSA_OPT_IV_SLAB:
+        if (value != 0 && value != 1) return fail(c, RSA_EINVAL, "bad interval-slab flag");
+        c->opt_ivslab = value;
+        return RSA_OK;
     default: return fail(c, RSA_EINVAL, "unknown option");
     }
 }
@@ -449,6 +455,7 @@ int rsa_get_option(rsa_ctx *c, int option, int64_t *value)
     case RSA_OPT_GRAPH: *value = c->opt_graph; return RSA_OK;
     case RSA_OPT_SLOTS: *value = c->opt_slots; return RSA_OK;
     case RSA_OPT_PROFILE: *value = c->opt_prof; return RSA_OK;
+    case RSA_OPT_IV_SLAB: *value = c->opt_ivslab; return RSA_OK;
     default: return fail(c, RSA_EINVAL, "unknown option");
     }
 }
@@ -524,7 +531,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
         while (j < ne && keys[order[j]] == keys[order[i]] && ent_pass[order[j]] == ent_pass[order[i]]) {
             const rsa_sample_t &x = s[ent_sample[order[j]]];
             stride = std::max(stride, sample_slab(x.L, x.k, tiles[ent_sample[order[j]]]));
-            lds = std::max(lds, sample_lds(x.L, x.k, tiles[ent_sample[order[j]]], c->lds_max));
+            lds = std::max(lds, sample_lds(x.L, x.k, tiles[ent_sample[order[j]]], interval_lds_max(c)));
             ++j;
         }
         g.count = j - i;
@@ -594,7 +601,7 @@ int rsa_run_batch(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, void *hip_strea
     }
     for (uint32_t i = 0; i < ne; ++i) {
         const uint32_t si = ent_sample[order[i]];
-        b->h_desc[i] = make_dev_desc(s[si], si, tiles[si], c->lds_max);
+        b->h_desc[i] = make_dev_desc(s[si], si, tiles[si], interval_lds_max(c));
         if (ent_pass[order[i]]) b->h_desc[i].flags |= kDescSizesPass;
     }
     HIP_TRY(c, hipEventCreate(&b->ev_start));
@@ -823,7 +830,7 @@ int rsa_run_batch_static(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, rsa_resu
         while (j < n && key[order[j]] == key[order[i]]) {
             const rsa_sample_t &x = s[order[j]];
             stride = std::max(stride, sample_slab(x.L, x.k, tile[order[j]]));
-            lds = std::max(lds, sample_lds(x.L, x.k, tile[order[j]], c->lds_max));
+            lds = std::max(lds, sample_lds(x.L, x.k, tile[order[j]], interval_lds_max(c)));
             ++j;
         }
         StaticGroup g;
@@ -855,7 +862,7 @@ int rsa_run_batch_static(rsa_ctx *c, const rsa_sample_t *s, uint32_t n, rsa_resu
         StageArgs sa;
         sa.n = std::min<uint32_t>(kStageDescs, n - i0);
         sa.dst = d_desc + i0;
-        for (uint32_t q = 0; q < sa.n; ++q) sa.d[q] = make_dev_desc(s[order[i0 + q]], order[i0 + q], tile[order[i0 + q]], c->lds_max);
+        for (uint32_t q = 0; q < sa.n; ++q) sa.d[q] = make_dev_desc(s[order[i0 + q]], order[i0 + q], tile[order[i0 + q]], interval_lds_max(c));
         void *sargs[] = {&sa};
         HIP_TRY(c, hipLaunchKernel((const void *)&rsa_stage_descs, dim3(1), dim3(kStageDescs), sargs, 0, stream));
     }

@@ -103,6 +103,7 @@ struct rsa_ctx {
     std::vector<rsa::Block> pinned; // free pinned host buffers (descriptor / result staging)
     std::vector<rsa::GraphEntry> graphs;
     int64_t opt_mode = RSA_MODE_BATCHED, opt_tile = -1, opt_graph = 1, opt_slots = 0, opt_prof = 0;
+    int64_t opt_ivslab = 0;
     int clock_khz = 0;
     hipStream_t plain[rsa::kPlainStreams] = {};
     hipEvent_t fork = nullptr, join[rsa::kPlainStreams] = {};
@@ -142,6 +143,9 @@ bool use_interval(uint32_t L, uint32_t k, int tile);
 // Whether the interval clear's difference counts fit the workgroup's LDS
 // beside the row counts (else they live in the slab).
 bool interval_in_lds(uint32_t L, uint32_t k, size_t lds_max);
+// The LDS bound the interval clear's difference counts are placed against:
+// the device's, or 0 with RSA_OPT_IV_SLAB (counts in the slab).
+size_t interval_lds_max(const rsa_ctx *c);
 // Whether a sample keeps the compressed lattice (occupancy and anchor bitmaps
 // instead of the int32 site map): sparse-clear tiles with k >= kCompressMinK.
 bool use_compressed(uint32_t L, uint32_t k, int tile);

@@ -94,7 +94,7 @@ struct rsa_server {
 
 namespace {
 
-uint32_t lds_bytes(const rsa_ctx *c, const rsa_sample_t &s, int tile) { return sample_lds(s.L, s.k, tile, c->lds_max); }
+uint32_t lds_bytes(const rsa_ctx *c, const rsa_sample_t &s, int tile) { return sample_lds(s.L, s.k, tile, interval_lds_max(c)); }
 
 // Kernel group of a sample: (waves, rows wider than 64 words, sparse clear,
 // contact census) select the kernel; the last bit splits lattices up to
@@ -222,7 +222,7 @@ int launch(rsa_server *v)
     const uint32_t n = (uint32_t)live.size();
     for (uint32_t i = 0; i < n; ++i) {
         Sample &sm = v->samples[live[i]];
-        DevDesc d = make_dev_desc(sm.s, i, sm.tile, c->lds_max);
+        DevDesc d = make_dev_desc(sm.s, i, sm.tile, interval_lds_max(c));
         d.slab = (uint64_t)(uintptr_t)(v->arena_base + sm.off);
         if (!sm.listed) d.flags |= kDescFresh;
         sm.listed = true;

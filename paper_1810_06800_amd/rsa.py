@@ -26,7 +26,7 @@ FLAG_TRACK_CLUSTERS = 2
 FLAG_CONTACTS = 4
 FLAG_CLUSTER_SIZES = 8
 SIZE_BINS = 32
-OPT_MODE, OPT_TILE, OPT_GRAPH, OPT_SLOTS, OPT_PROFILE = 1, 2, 3, 4, 5
+OPT_MODE, OPT_TILE, OPT_GRAPH, OPT_SLOTS, OPT_PROFILE, OPT_IV_SLAB = 1, 2, 3, 4, 5, 6
 PROFILE_SLOTS = ("init", "sel_total", "sel_ring", "sel_select", "sel_clear", "lab_total", "lab_idle",
                  "lab_map", "lab_gather", "lab_resolve", "lab_merge", "lab_writeback",
                  "lab_batches", "lab_edges", "lab_flushes", "steps", "spec_hits", "sel_hook",

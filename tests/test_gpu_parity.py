@@ -393,6 +393,43 @@ def test_long_kmers_interval_clear_and_compressed_lattice(ctx, orc):
         ctx.set_option(rsa.OPT_TILE, -1)
 
 
+def test_interval_counts_in_the_slab(ctx, orc):
+    """The interval clear with its difference counts in the slab, in two sets
+    used by alternate steps (the layout L = 32768 needs), forced on shapes
+    whose counts would fit LDS: narrow and wide rows, ragged L % 64, k = L,
+    k near L/2, every statistic flag, several selecting-wave counts, and
+    samples of L = 16384, k = 1024 against the stored oracle results."""
+    import json
+
+    from paper_1810_06800_amd import rsa
+
+    descs = [(512, 512, 3, 0, 0), (600, 512, 3, 1, 2), (1000, 513, 4, 0, 4), (1024, 600, 4, 1, 0),
+             (1500, 700, 5, 0, 6), (2048, 512, 5, 1, 0), (2999, 1499, 6, 0, 2), (4100, 1025, 6, 1, 4)]
+    descs += [(1100, 550, 9, s, 0) for s in range(4)]
+    want = orc.run_many(descs, threads=min(16, os.cpu_count() or 1))
+    with open(os.path.join(os.path.dirname(__file__), "golden", "large_expected.json")) as f:
+        golden = json.load(f)
+    big = [tuple(d) for d in golden["descs"] if d[0] == 16384][:4]
+    big_want = {tuple(d): r for d, r in zip(golden["descs"], golden["results"])}
+    ctx.set_option(rsa.OPT_IV_SLAB, 1)
+    try:
+        assert ctx.get_option(rsa.OPT_IV_SLAB) == 1
+        _log(f"interval counts in the slab: {len(descs)} samples, default tiles")
+        check(descs, ctx.run(descs), want, census=True)
+        _log(f"interval counts in the slab: {len(big)} samples of L = 16384")
+        check(big, ctx.run(big), [big_want[d] for d in big])
+        for waves in (1, 2, 7):
+            tile = rsa.tile_for_shape(1024, 600)
+            w0, tr, mr, sp = rsa.tile_shape(tile)
+            t = next(t for t in range(rsa.num_tiles()) if rsa.tile_shape(t) == (waves, tr, mr, sp))
+            ctx.set_option(rsa.OPT_TILE, t)
+            _log(f"interval counts in the slab: tile {t} ({rsa.tile_shape(t)})")
+            check(descs[:6], ctx.run(descs[:6]), want[:6], census=True)
+    finally:
+        ctx.set_option(rsa.OPT_TILE, -1)
+        ctx.set_option(rsa.OPT_IV_SLAB, 0)
+
+
 def test_small_budget_reuses_slabs(orc):
     """A context whose memory budget holds only a few slabs runs a larger
     batch with a few workgroups, each taking sample after sample on the same
