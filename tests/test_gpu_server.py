@@ -96,6 +96,31 @@ def test_time_sliced_runs_are_exact(ctx, orc):
     assert st["launches"] > 50   # the long samples were sliced
 
 
+def test_time_sliced_long_kmers_with_slab_counts(ctx, orc):
+    """Long k-mers (interval clear, compressed lattice) yielding and resuming
+    at a 20 us quantum, with the interval clear's counts forced into the slab
+    (two sets used by alternate steps, both cleared when a sample resumes)."""
+    from paper_1810_06800_amd import rsa
+
+    reqs = [[(1100, 512, 21, s, 0) for s in range(2)], [(1500, 700, 22, 0, 2)], [(2048, 600, 23, 1, 4)],
+            [(600, 512, 24, 0, 0)]]
+    ctx.set_option(rsa.OPT_IV_SLAB, 1)
+    try:
+        _log("server: long k-mers, counts in the slab, quantum 20 us")
+        with rsa.Server(ctx, arena_bytes=1 << 30, quantum_us=20) as srv:
+            got = srv.run(reqs)
+            st = srv.stats()
+    finally:
+        ctx.set_option(rsa.OPT_IV_SLAB, 0)
+    flat = [d for r in reqs for d in r]
+    want = orc.run_many(flat, threads=min(16, os.cpu_count() or 1))
+    same_as_oracle(flat, [g for r in got for g in r], want)
+    for d, g in zip(flat, [g for r in got for g in r]):
+        if d[4] & 4:
+            assert (g["n_contacts_x"], g["n_contacts_y"], g["n_contacts_xy"]) == orc.contacts_at_jamming(*d)
+    assert st["launches"] > 20   # the samples were sliced
+
+
 def test_alone_and_in_the_mix_agree(ctx):
     """Each request gives the same results alone, in a mix that arrives while
     it runs, and through rsa_run_batch."""
